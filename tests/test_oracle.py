@@ -1,0 +1,447 @@
+"""Pins of the FP64 CPU oracle against what the mathematics fixes (CPU only).
+
+Each check is chosen so that a plausible slip in the oracle (a dropped term, a
+wrong index or sign, a transposed operand, an off-by-one in the iteration
+count) fails at least one of them.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import oracle
+from synth import (banded_spd, dense_spd, dense_to_csr, kershaw4, laplacian7, q1_elasticity,
+                   spectrum_spd, tridiagonal_spd, build_config)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def csr_of(M, pattern=None):
+    return dense_to_csr(M, pattern)
+
+
+def lower_dense(lrp, lci, lv, n):
+    return sp.csr_matrix((lv, lci, lrp), shape=(n, n)).toarray()
+
+
+# ------------------------------------------------------------------ IC(0)
+
+@pytest.mark.parametrize("n", [1, 2, 7, 40])
+def test_ic0_tridiagonal_is_cholesky(n):
+    M = tridiagonal_spd(n, seed=n)
+    st, L, alpha, _, _ = oracle.ic0_shifted(*csr_of(M))
+    assert st == oracle.OK and alpha == 0.0
+    Ld = lower_dense(*L, n)
+    C = np.linalg.cholesky(M)
+    assert np.abs(Ld - C).max() <= 1e-14 * np.abs(C).max()
+
+
+@pytest.mark.parametrize("n", [3, 12, 30])
+def test_ic0_full_pattern_is_cholesky(n):
+    M = dense_spd(n, seed=n, cond=1e3)
+    st, L, alpha, _, _ = oracle.ic0_shifted(*csr_of(M, np.ones((n, n), bool)))
+    assert st == oracle.OK and alpha == 0.0
+    C = np.linalg.cholesky(M)
+    assert np.abs(lower_dense(*L, n) - C).max() <= 1e-12 * np.abs(C).max()
+
+
+def test_ic0_full_band_is_cholesky():
+    n, bw = 25, 3
+    M = banded_spd(n, bw, seed=1)
+    pat = np.abs(np.subtract.outer(np.arange(n), np.arange(n))) <= bw
+    st, L, alpha, _, _ = oracle.ic0_shifted(*csr_of(M, pat))
+    assert st == oracle.OK and alpha == 0.0
+    C = np.linalg.cholesky(M)
+    assert np.abs(lower_dense(*L, n) - C).max() <= 1e-13 * np.abs(C).max()
+
+
+def test_ic0_diagonal_is_sqrt():
+    d = np.array([4.0, 9.0, 2.0, 0.25])
+    st, L, _, _, mp = oracle.ic0_shifted(*csr_of(np.diag(d)))
+    assert st == oracle.OK
+    assert np.array_equal(L[2], np.sqrt(d))
+    assert mp == 0.25
+
+
+@pytest.mark.parametrize("E", [2, 3])
+def test_ic0_defining_identity_on_pattern(E):
+    """(L L^T)_ij = A_ij on every stored lower entry; off the pattern LL^T may differ."""
+    p = q1_elasticity(E, 2.0, 21)
+    st, L, alpha, _, _ = oracle.ic0_shifted(p.row_ptr, p.col, p.val)
+    assert st == oracle.OK
+    n = p.n
+    Ld = lower_dense(*L, n)
+    A = p.to_scipy().toarray() + alpha * np.diag(np.diag(p.to_scipy().toarray()))
+    P = Ld @ Ld.T
+    lrp, lci, _ = L
+    rows = np.repeat(np.arange(n), np.diff(lrp))
+    err = np.abs(P[rows, lci] - A[rows, lci])
+    assert err.max() <= 1e-12 * np.abs(A).max()
+    # lower triangular with positive diagonal, on exactly tril(A)'s stored pattern
+    assert np.all(np.diag(Ld) > 0)
+    T = sp.tril(p.to_scipy()).tocsr()
+    T.sort_indices()
+    assert np.array_equal(lrp, T.indptr) and np.array_equal(lci, T.indices)
+    assert lci.shape[0] == (p.nnz + n) // 2
+
+
+def test_ic0_kershaw_breakdown_and_shift():
+    g = json.load(open(os.path.join(GOLDEN, "kershaw4.json")))
+    A = np.array(g["A"], float)
+    assert np.all(np.linalg.eigvalsh(A) > 0)
+    C = np.linalg.cholesky(A)
+    assert np.allclose(np.diag(C) ** 2, g["cholesky_pivots_squared"], rtol=1e-14)
+    rp, ci, v = csr_of(A)
+    lrp, lci, lv = oracle.tril(rp, ci, v)
+    st, L, fr, mp = oracle.ic0(lrp, lci, lv, 0.0)
+    assert st == oracle.PIVOT
+    assert fr == g["ic0_fail_row"]
+    assert abs(mp - g["ic0_pivots_squared"][3]) < 1e-13
+    # the shift rule recovers, and the shifted factor satisfies the identity for A + alpha diag(A)
+    st, L, alpha, restarts, _ = oracle.ic0_shifted(rp, ci, v)
+    assert st == oracle.OK and alpha > 0 and restarts >= 1
+    seq = [0.0] + [1e-3 * 2 ** k for k in range(40)]
+    assert alpha == seq[restarts]
+    Ld = lower_dense(*L, 4)
+    As = A + alpha * np.diag(np.diag(A))
+    P = Ld @ Ld.T
+    for i in range(4):
+        for q in range(L[0][i], L[0][i + 1]):
+            j = L[1][q]
+            assert abs(P[i, j] - As[i, j]) < 1e-13
+    # one step earlier in the shift sequence still fails
+    st_prev, *_ = oracle.ic0(lrp, lci, lv, seq[restarts - 1])
+    assert st_prev == oracle.PIVOT
+
+
+def test_ic0_laplacian_never_shifts():
+    rp, ci, v = laplacian7(6, 5, 4)
+    st, L, alpha, restarts, mp = oracle.ic0_shifted(rp, ci, v)
+    assert st == oracle.OK and alpha == 0.0 and restarts == 0 and mp > 0
+
+
+def test_tril_and_transpose_against_scipy():
+    p = q1_elasticity(3, 1.0, 2)
+    lrp, lci, lv = oracle.tril(p.row_ptr, p.col, p.val)
+    T = sp.tril(p.to_scipy()).tocsr()
+    T.sort_indices()
+    assert np.array_equal(lrp, T.indptr) and np.array_equal(lci, T.indices)
+    assert np.array_equal(lv, T.data)
+    urp, uci, uv = oracle.transpose(lrp, lci, lv)
+    U = T.T.tocsr()
+    U.sort_indices()
+    assert np.array_equal(urp, U.indptr) and np.array_equal(uci, U.indices)
+    assert np.array_equal(uv, U.data)
+
+
+# ------------------------------------------------------------------ levels
+
+def q1_levels_closed_form(E):
+    N1 = E + 1
+    K_, J_, I_ = np.meshgrid(np.arange(E), np.arange(N1), np.arange(N1), indexing="ij")
+    i = np.repeat(I_.reshape(-1), 3); j = np.repeat(J_.reshape(-1), 3); k = np.repeat(K_.reshape(-1), 3)
+    d = np.tile(np.arange(3), N1 * N1 * E)
+    lo = 3 * (i + 2 * j + 4 * k) + d
+    up = 3 * ((E - i) + 2 * (E - j) + 4 * (E - 1 - k)) + (2 - d)
+    return lo, up
+
+
+@pytest.mark.parametrize("E", [1, 2, 3, 4, 5])
+def test_levels_q1_closed_form(E):
+    p = q1_elasticity(E, 1.0, 1)
+    lrp, lci, _ = oracle.tril(p.row_ptr, p.col, p.val)
+    lev, nl = oracle.levels_lower(lrp, lci)
+    levu, nlu = oracle.levels_upper(lrp, lci)
+    lo, up = q1_levels_closed_form(E)
+    assert nl == 21 * E - 9 and nlu == 21 * E - 9
+    assert np.array_equal(lev, lo)
+    assert np.array_equal(levu, up)
+
+
+def test_levels_properties_and_sort():
+    p = q1_elasticity(4, 1.0, 1)
+    lrp, lci, _ = oracle.tril(p.row_ptr, p.col, p.val)
+    lev, nl = oracle.levels_lower(lrp, lci)
+    levu, nlu = oracle.levels_upper(lrp, lci)
+    rows = np.repeat(np.arange(p.n), np.diff(lrp))
+    off = lci < rows
+    # every dependency sits on a strictly lower level; the level is tight
+    assert np.all(lev[lci[off]] < lev[rows[off]])
+    assert np.all(levu[rows[off]] < levu[lci[off]])
+    tight = np.full(p.n, -1)
+    np.maximum.at(tight, rows[off], lev[lci[off]])
+    assert np.array_equal(lev, tight + 1)
+    perm, lp = oracle.level_sort(lev, nl)
+    assert np.array_equal(perm, np.lexsort((np.arange(p.n), lev)))
+    assert np.array_equal(lp, np.concatenate([[0], np.cumsum(np.bincount(lev, minlength=nl))]))
+
+
+def test_levels_special_patterns():
+    M = tridiagonal_spd(9)
+    lrp, lci, _ = oracle.tril(*csr_of(M))
+    lev, nl = oracle.levels_lower(lrp, lci)
+    assert nl == 9 and np.array_equal(lev, np.arange(9))
+    levu, nlu = oracle.levels_upper(lrp, lci)
+    assert nlu == 9 and np.array_equal(levu, np.arange(9)[::-1])
+    lrp, lci, _ = oracle.tril(*csr_of(np.diag(np.arange(1.0, 6.0))))
+    assert oracle.levels_lower(lrp, lci)[1] == 1
+    assert oracle.levels_upper(lrp, lci)[1] == 1
+
+
+# --------------------------------------------------------- triangular solves
+
+def test_trsv_against_scipy_solve_triangular():
+    rng = np.random.default_rng(5)
+    n = 30
+    M = np.tril(rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.3), -1)
+    M += np.diag(1.0 + rng.random(n))
+    lrp, lci, lv = csr_of(M)
+    r = rng.standard_normal(n)
+    y = oracle.trsv_lower(lrp, lci, lv, r)
+    assert np.allclose(y, sla.solve_triangular(M, r, lower=True), rtol=1e-13, atol=1e-13)
+    urp, uci, uv = oracle.transpose(lrp, lci, lv)
+    z = oracle.trsv_upper(urp, uci, uv, y)
+    assert np.allclose(z, sla.solve_triangular(M.T, y, lower=False), rtol=1e-13, atol=1e-13)
+
+
+def test_trsv_residual_on_factor():
+    p = q1_elasticity(4, 2.0, 9)
+    st, L, _, _, _ = oracle.ic0_shifted(p.row_ptr, p.col, p.val)
+    r = np.random.default_rng(1).standard_normal(p.n)
+    y = oracle.trsv_lower(*L, r)
+    Ls = sp.csr_matrix((L[2], L[1], L[0]), shape=(p.n, p.n))
+    assert np.linalg.norm(Ls @ y - r) / np.linalg.norm(r) < 1e-13
+    U = oracle.transpose(*L)
+    z = oracle.trsv_upper(*U, y)
+    assert np.linalg.norm(Ls.T @ z - y) / np.linalg.norm(y) < 1e-13
+
+
+def test_spmv_against_dense():
+    p = q1_elasticity(3, 1.0, 4)
+    x = np.random.default_rng(2).standard_normal(p.n)
+    w = oracle.spmv(p.row_ptr, p.col, p.val, x)
+    assert np.allclose(w, p.to_scipy().toarray() @ x, rtol=1e-13, atol=1e-12)
+
+
+# --------------------------------------------------------------------- PCG
+
+def _identity_factor(n):
+    I = np.eye(n)
+    L = csr_of(I)
+    return L, oracle.transpose(*L)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8])
+def test_pcg_k_distinct_eigenvalues(k):
+    """CG on A with k distinct eigenvalues reaches the solution after k products."""
+    n = 50
+    lam = np.linspace(1.0, 10.0, k)
+    M = spectrum_spd(n, lam, seed=k)
+    A = csr_of(M, np.ones((n, n), bool))
+    L, U = _identity_factor(n)
+    b = np.random.default_rng(k).standard_normal(n)
+    res = oracle.pcg(A, L, U, b, rtol=1e-10, max_replace=0)
+    assert res["status"] == oracle.OK
+    assert res["iters"] == k
+    assert np.allclose(res["x"], np.linalg.solve(M, b), rtol=1e-8)
+
+
+def test_pcg_exact_factor_one_iteration():
+    n = 40
+    M = dense_spd(n, seed=3, cond=1e4)
+    A = csr_of(M, np.ones((n, n), bool))
+    st, L, _, _, _ = oracle.ic0_shifted(*A)
+    U = oracle.transpose(*L)
+    b = np.random.default_rng(0).standard_normal(n)
+    res = oracle.pcg(A, L, U, b, rtol=1e-10)
+    assert res["iters"] == 1 and res["status"] == oracle.OK
+    assert np.linalg.norm(res["x"] - np.linalg.solve(M, b)) <= 1e-10 * np.linalg.norm(res["x"])
+
+
+def test_pcg_zero_rhs_and_exact_start():
+    p = q1_elasticity(2, 1.0, 3)
+    A = (p.row_ptr, p.col, p.val)
+    st, L, _, _, _ = oracle.ic0_shifted(*A)
+    U = oracle.transpose(*L)
+    res = oracle.pcg(A, L, U, np.zeros(p.n), x0=np.ones(p.n))
+    assert res["iters"] == 0 and res["status"] == oracle.OK and np.all(res["x"] == 0)
+    xs = np.linalg.solve(p.to_scipy().toarray(), np.ones(p.n))
+    res = oracle.pcg(A, L, U, np.ones(p.n), x0=xs, rtol=1e-6)
+    assert res["iters"] == 0
+
+
+def test_pcg_solution_and_residual_config0():
+    prob, b = build_config(0)
+    A = (prob.row_ptr, prob.col, prob.val)
+    st, L, alpha, _, _ = oracle.ic0_shifted(*A)
+    U = oracle.transpose(*L)
+    res = oracle.pcg(A, L, U, b, rtol=1e-8)
+    assert res["status"] == oracle.OK and 5 < res["iters"] < 200
+    D = prob.to_scipy().toarray()
+    xs = np.linalg.solve(D, b)
+    assert np.linalg.norm(D @ res["x"] - b) / np.linalg.norm(b) <= 1e-8
+    kappa = np.linalg.cond(D)
+    assert np.linalg.norm(res["x"] - xs) / np.linalg.norm(xs) <= kappa * 1e-8
+    assert res["true_relres"] <= 1e-8
+
+
+def test_pcg_a_norm_bound_eq6():
+    """A-norm form of the CG error bound (Eq. 6) with kappa of L^-1 A L^-T."""
+    p = q1_elasticity(2, 1.0, 8)
+    A = (p.row_ptr, p.col, p.val)
+    st, L, _, _, _ = oracle.ic0_shifted(*A)
+    U = oracle.transpose(*L)
+    n = p.n
+    D = p.to_scipy().toarray()
+    Ld = lower_dense(*L, n)
+    Li = np.linalg.inv(Ld)
+    ev = np.linalg.eigvalsh(Li @ D @ Li.T)
+    kappa = ev[-1] / ev[0]
+    q = (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)
+    b = np.random.default_rng(3).standard_normal(n)
+    xs = np.linalg.solve(D, b)
+    e0 = np.sqrt(xs @ D @ xs)
+    for l in range(1, 12):
+        res = oracle.pcg(A, L, U, b, rtol=0.0, max_iter=l, max_replace=0)
+        assert res["status"] == oracle.MAXITER and res["iters"] == l
+        e = res["x"] - xs
+        assert np.sqrt(e @ D @ e) <= 2 * e0 * q ** l * (1 + 1e-8) + 1e-12
+
+
+def test_pcg_failure_statuses():
+    n = 4
+    L, U = _identity_factor(n)
+    # indefinite A: p^T A p <= 0 on the first step
+    M = np.diag([1.0, -3.0, 1.0, 1.0])
+    res = oracle.pcg(csr_of(M), L, U, np.ones(n))
+    assert res["status"] == oracle.BREAKDOWN
+    # non-finite input
+    res = oracle.pcg(csr_of(np.eye(n) * 2), L, U, np.array([1.0, np.nan, 0, 0]))
+    assert res["status"] == oracle.NONFINITE
+    # max_iter exhausted
+    p = q1_elasticity(2, 1.0, 3)
+    A = (p.row_ptr, p.col, p.val)
+    Lp = oracle.ic0_shifted(*A)[1]
+    res = oracle.pcg(A, Lp, oracle.transpose(*Lp), np.ones(p.n), rtol=1e-30, max_iter=7)
+    assert res["status"] == oracle.MAXITER and res["iters"] == 7
+
+
+def test_pcg_iteration_count_convention():
+    """Iterations = products A p: the listing's pre-loop step is iteration 1, so a
+    2-eigenvalue problem stops at exactly 2 and max_iter=1 stops after one product."""
+    n = 20
+    M = spectrum_spd(n, [1.0, 4.0], seed=1)
+    A = csr_of(M, np.ones((n, n), bool))
+    L, U = _identity_factor(n)
+    b = np.random.default_rng(9).standard_normal(n)
+    r1 = oracle.pcg(A, L, U, b, rtol=0.0, max_iter=1, max_replace=0)
+    # after one step of CG from 0 the iterate is the steepest-descent step alpha b
+    alpha = (b @ b) / (b @ M @ b)
+    assert np.allclose(r1["x"], alpha * b, rtol=1e-13)
+    r2 = oracle.pcg(A, L, U, b, rtol=1e-12, max_replace=0)
+    assert r2["iters"] == 2
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_pcg_reduced_precision_factor_config0(prec):
+    prob, b = build_config(0)
+    A = (prob.row_ptr, prob.col, prob.val)
+    st, L, _, _, _ = oracle.ic0_shifted(*A)
+    U = oracle.transpose(*L)
+    ref = oracle.pcg(A, L, U, b, rtol=1e-8)
+    res = oracle.pcg(A, L, U, b, rtol=1e-8, prec=prec)
+    assert res["status"] == oracle.OK
+    assert res["true_relres"] <= 1e-8
+    err = np.linalg.norm(res["x"] - ref["x"]) / np.linalg.norm(ref["x"])
+    assert err < 1e-6
+    assert abs(res["iters"] - ref["iters"]) <= (3 if prec == 1 else 30)
+
+
+def test_round_bf16_against_torch():
+    import torch
+    assert oracle.round_bf16(1.0) == 1.0
+    assert oracle.round_bf16(1.0 + 2 ** -8) == 1.0                 # tie to even
+    assert oracle.round_bf16(1.0 + 3 * 2 ** -8) == 1.0 + 2 ** -6    # tie to even (up)
+    x = np.random.default_rng(0).standard_normal(20000).astype(np.float32) * 1e3
+    got = oracle.cast_values(x.astype(np.float64), 2)
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(got, want)
+    got32 = oracle.cast_values(x.astype(np.float64), 1)
+    assert np.array_equal(got32, x)
+
+
+def test_apply_f32_close_to_f64():
+    p = q1_elasticity(3, 1.0, 5)
+    st, L, _, _, _ = oracle.ic0_shifted(p.row_ptr, p.col, p.val)
+    U = oracle.transpose(*L)
+    r = np.random.default_rng(0).standard_normal(p.n)
+    _, z = oracle.apply(L, U, r)
+    z32 = oracle.apply_f32(L, U, r, 1)
+    z16 = oracle.apply_f32(L, U, r, 2)
+    e32 = np.linalg.norm(z32 - z) / np.linalg.norm(z)
+    e16 = np.linalg.norm(z16 - z) / np.linalg.norm(z)
+    assert 0 < e32 < 1e-5
+    assert e32 < e16 < 1e-1
+
+
+# ----------------------------------------------------------------- adjoint
+
+def test_adjoint_diagonal_closed_form():
+    l = np.array([1.5, 2.0, 0.7])
+    r = np.array([0.3, -1.0, 2.0])
+    g = np.array([1.0, 0.5, -2.0])
+    L = csr_of(np.diag(l))
+    U = oracle.transpose(*L)
+    out = oracle.apply_adjoint(L, U, r[:, None], g[:, None])
+    assert np.allclose(out["Z"][:, 0], r / l ** 2, rtol=1e-15)
+    # z_i = r_i / l_i^2  =>  dl/dl_i = -2 g_i r_i / l_i^3,  dl/dr_i = g_i / l_i^2
+    assert np.allclose(out["dL"], -2 * g * r / l ** 3, rtol=1e-14)
+    assert np.allclose(out["Rbar"][:, 0], g / l ** 2, rtol=1e-15)
+
+
+def test_adjoint_central_differences():
+    p = q1_elasticity(2, 1.0, 6)
+    st, L, _, _, _ = oracle.ic0_shifted(p.row_ptr, p.col, p.val)
+    lrp, lci, lv = L
+    n, m = p.n, 3
+    rng = np.random.default_rng(4000)
+    R = rng.standard_normal((n, m))
+    W = rng.standard_normal((n, m))
+
+    def loss(vals, Rm):
+        Lx = (lrp, lci, vals)
+        Z = oracle.apply_adjoint(Lx, oracle.transpose(*Lx), Rm, np.zeros_like(Rm))["Z"]
+        return float(np.sum(W * Z) + 0.5 * np.sum(Z * Z))
+
+    Z = oracle.apply_adjoint(L, oracle.transpose(*L), R, np.zeros_like(R))["Z"]
+    G = W + Z
+    out = oracle.apply_adjoint(L, oracle.transpose(*L), R, G)
+    h = 1e-6
+    for q in rng.choice(lv.shape[0], 20, replace=False):
+        vp = lv.copy(); vp[q] += h
+        vm = lv.copy(); vm[q] -= h
+        fd = (loss(vp, R) - loss(vm, R)) / (2 * h)
+        assert abs(fd - out["dL"][q]) <= 1e-6 * abs(fd) + 1e-7, (q, fd, out["dL"][q])
+    for (i, k) in [(0, 0), (n // 2, 1), (n - 1, 2)]:
+        Rp = R.copy(); Rp[i, k] += h
+        Rm = R.copy(); Rm[i, k] -= h
+        fd = (loss(lv, Rp) - loss(lv, Rm)) / (2 * h)
+        assert abs(fd - out["Rbar"][i, k]) <= 1e-6 * abs(fd) + 1e-7
+
+
+def test_adjoint_rbar_is_apply_of_g():
+    p = q1_elasticity(2, 1.0, 6)
+    st, L, _, _, _ = oracle.ic0_shifted(p.row_ptr, p.col, p.val)
+    U = oracle.transpose(*L)
+    G = np.random.default_rng(1).standard_normal((p.n, 2))
+    R = np.random.default_rng(2).standard_normal((p.n, 2))
+    out = oracle.apply_adjoint(L, U, R, G)
+    for k in range(2):
+        _, z = oracle.apply(L, U, G[:, k])
+        assert np.array_equal(out["Rbar"][:, k], z)
+    # symmetric operator: <G, apply(R)> == <apply(G), R>
+    assert abs(np.sum(G * out["Z"]) - np.sum(out["Rbar"] * R)) < 1e-10 * np.abs(np.sum(G * out["Z"]))
