@@ -19,7 +19,8 @@
  * Conventions: CSR with int64 row pointers, int32 column indices ascending in
  * every row, FP64 values. Triangular factors store the diagonal in every row:
  * last in a lower row, first in an upper row. Every sum runs sequentially in
- * ascending index order. Build with -ffp-contract=off (no fused multiply-add)
+ * ascending index order (inner products with compensation, see orc_dot).
+ * Build with -ffp-contract=off (no fused multiply-add)
  * and without fast-math so each operation is one IEEE-754 rounding.
  */
 #include <math.h>
@@ -48,10 +49,22 @@ void orc_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
   }
 }
 
+/* Inner product sum_i a_i b_i (the r^T z, p^T w and ||r||^2 of supplementary
+ * Algorithm 1). The paper fixes no summation order; the products are summed in
+ * ascending index order with Neumaier's compensation, so the result is close
+ * to the exactly rounded inner product (plain running sums over 1e5+ terms
+ * carry enough error to move the iteration at which CG crosses the
+ * tolerance). */
 double orc_dot(int64_t n, const double *a, const double *b) {
-  double s = 0.0;
-  for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
-  return s;
+  double s = 0.0, c = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double x = a[i] * b[i];
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+  }
+  return s + c;
 }
 
 /* Checks the CSR invariants the solver relies on: row pointers

@@ -445,3 +445,17 @@ def test_adjoint_rbar_is_apply_of_g():
         assert np.array_equal(out["Rbar"][:, k], z)
     # symmetric operator: <G, apply(R)> == <apply(G), R>
     assert abs(np.sum(G * out["Z"]) - np.sum(out["Rbar"] * R)) < 1e-10 * np.abs(np.sum(G * out["Z"]))
+
+
+def test_dot_is_nearly_exactly_rounded():
+    """The inner product matches the correctly rounded sum (math.fsum of the
+    rounded products) even under heavy cancellation."""
+    import math
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal(200000) * np.exp(rng.uniform(-20, 20, 200000))
+    b = rng.standard_normal(200000)
+    a = np.concatenate([a, -a[:1000]]); b = np.concatenate([b, b[:1000]])
+    exact = math.fsum(a * b)
+    got = oracle.dot(a, b)
+    assert abs(got - exact) <= 4 * np.finfo(float).eps * math.fsum(np.abs(a * b))
+    assert oracle.dot(np.ones(10), np.arange(10.0)) == 45.0
