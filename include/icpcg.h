@@ -1,0 +1,241 @@
+/*
+ * icpcg.h — C ABI of an MI355X (gfx950) library for incomplete-Cholesky
+ * preconditioned conjugate gradients on sparse symmetric positive definite
+ * matrices.
+ *
+ * The problem follows Li, Wang, Wang, "Deep Learning-Enhanced Preconditioning
+ * for Efficient Conjugate Gradient Solvers in Large-Scale PDE Systems":
+ *   - solve A x = b, A sparse SPD (Introduction);
+ *   - preconditioner P = L L^T with L lower triangular on the pattern of
+ *     tril(A) (Model Architecture section, IC(0); supplementary section 2);
+ *     L comes from icpcg_factor() or from the caller (for example a learned
+ *     correction L = L_IC + GNN(A), Eq. (2));
+ *   - PCG iteration of supplementary Algorithm 1, stopped on the relative
+ *     residual (Evaluation Metrics section);
+ *   - P-time (factor) and CG-time (solve) are separate calls (supplementary
+ *     section 2, total time T_p + l * t_cg).
+ *
+ * Conventions for every call
+ *   - Matrices are CSR: row_ptr int64[n+1] (row_ptr[0] = 0), col int32[nnz]
+ *     strictly ascending inside each row, values in the stated type. Every
+ *     row stores its diagonal. A lower factor keeps its diagonal last in each
+ *     row.
+ *   - Multi-column blocks (nrhs columns) are row-major n x nrhs: entry (i, k)
+ *     at i * nrhs + k. One column is a plain vector.
+ *   - Every matrix, vector and block pointer is a DEVICE pointer owned by the
+ *     caller; the caller keeps it alive until the call returns. Handles are
+ *     owned by the library and released by the matching *_destroy call.
+ *   - All work is enqueued on the context's HIP stream. Calls that return
+ *     information (icpcg_factor, icpcg_solve, icpcg_tril_nnz, ...) synchronize
+ *     that stream before returning; pure kernels (icpcg_spmv, icpcg_apply,
+ *     icpcg_apply_backward, icpcg_trsv) return without synchronizing.
+ *   - Errors are reported as status codes; nothing aborts or throws across the
+ *     boundary. icpcg_last_error() gives a message for the last failing call on
+ *     a context.
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef ICPCG_H
+#define ICPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ICPCG_OK = 0,
+  ICPCG_E_INVALID = 1,       /* bad argument or malformed matrix */
+  ICPCG_E_PIVOT = 2,         /* IC(0) pivot <= 0 after all allowed shifts */
+  ICPCG_E_BREAKDOWN = 3,     /* PCG: r^T z <= 0 or p^T A p <= 0 */
+  ICPCG_E_MAXITER = 4,       /* PCG: iteration cap reached (x is the last iterate) */
+  ICPCG_E_NONFINITE = 5,     /* PCG: NaN or Inf met */
+  ICPCG_E_DEVICE = 6,        /* HIP runtime error or device-side wait limit hit */
+  ICPCG_E_NOMEM = 7,         /* device allocation failed */
+  ICPCG_E_TRUE_RESIDUAL = 8  /* recurrence converged but ||b - A x|| stayed above
+                                rtol ||b|| after the allowed residual replacements */
+} icpcg_status;
+
+/* Storage / arithmetic precision of the factor when it is applied. */
+typedef enum {
+  ICPCG_F64 = 0,  /* FP64 values, FP64 arithmetic */
+  ICPCG_F32 = 1,  /* FP32 values (round-to-nearest-even of FP64), FP32 arithmetic */
+  ICPCG_BF16 = 2  /* bfloat16 values (RNE of the FP32 copy), FP32 arithmetic */
+} icpcg_dtype;
+
+/* A square CSR matrix with FP64 values (device pointers). */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const double *val;
+} icpcg_csr;
+
+typedef struct icpcg_ctx icpcg_ctx;    /* stream, workspace, device properties */
+typedef struct icpcg_prec icpcg_prec;  /* L, L^T, schedules, reduced-precision copies */
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to the current HIP device and to `hip_stream`
+ * (a hipStream_t; NULL means the null stream). */
+icpcg_status icpcg_create(icpcg_ctx **ctx, void *hip_stream);
+icpcg_status icpcg_destroy(icpcg_ctx *ctx);
+/* Rebind the context to another stream of the same device. */
+icpcg_status icpcg_set_stream(icpcg_ctx *ctx, void *hip_stream);
+const char *icpcg_last_error(const icpcg_ctx *ctx);
+const char *icpcg_status_string(icpcg_status st);
+
+/* -------------------------------------------------------------- factor */
+
+/* Number of stored entries of tril(A) (diagonal included, explicit zeros
+ * counted): the size of the factor buffers icpcg_factor() fills. */
+icpcg_status icpcg_tril_nnz(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *nnz_lower);
+
+typedef struct {
+  int max_restarts;    /* shifts tried after alpha = 0 (default 30 when < 0) */
+  double alpha_min;    /* first nonzero shift (default 1e-3 when <= 0) */
+} icpcg_factor_opts;
+
+typedef struct {
+  double alpha;        /* shift used: factor of A + alpha diag(A) */
+  int restarts;        /* number of shifted restarts */
+  double min_pivot;    /* smallest squared pivot of the successful attempt */
+  int64_t nlevels;     /* level count of the row schedule of tril(A) */
+} icpcg_factor_info;
+
+/* IC(0): lower L on the pattern of tril(A) with (L L^T)_ij = A_ij on that
+ * pattern (Model Architecture section; zero fill). Computed in FP64 on the
+ * GPU, rows scheduled by level. A pivot that is not > 0 restarts on
+ * A + alpha diag(A) with alpha = 0, alpha_min, 2 alpha_min, 4 alpha_min, ...
+ * (the paper uses IC(0) as a black box; this global shift is this library's
+ * rule). Outputs L_row_ptr[n+1], L_col[nnz_lower], L_val[nnz_lower] (caller
+ * buffers sized by icpcg_tril_nnz). opts and info may be NULL.
+ * Errors: ICPCG_E_INVALID (malformed A, row of tril(A) longer than 4096),
+ * ICPCG_E_PIVOT (every shift failed; L holds the last attempt). */
+icpcg_status icpcg_factor(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *L_row_ptr,
+                          int32_t *L_col, double *L_val, const icpcg_factor_opts *opts,
+                          icpcg_factor_info *info);
+
+/* ------------------------------------------------------- preconditioner */
+
+/* Build a preconditioner from a lower-triangular CSR factor L (any lower
+ * pattern with a stored, positive diagonal; values FP64). The library copies
+ * what it needs (transpose L^T, supernode schedules, the FP32 or BF16 copy
+ * when apply_dtype asks for one), so L's buffers may be released afterwards.
+ * Errors: ICPCG_E_INVALID (not lower triangular, unsorted, missing or
+ * non-positive diagonal, non-finite value). */
+icpcg_status icpcg_prec_create(icpcg_ctx *ctx, const icpcg_csr *L, icpcg_dtype apply_dtype,
+                               icpcg_prec **P);
+icpcg_status icpcg_prec_destroy(icpcg_prec *P);
+
+/* Replace the factor's values (same pattern, FP64, CSR order of L) and
+ * refresh L^T and the reduced-precision copy. */
+icpcg_status icpcg_prec_update_values(icpcg_ctx *ctx, icpcg_prec *P, const double *L_val);
+
+typedef struct {
+  int64_t n, nnz;          /* of L */
+  int64_t nlevels_L;       /* row levels of forward substitution */
+  int64_t nlevels_U;       /* row levels of backward substitution */
+  int64_t nsupernodes_L;   /* schedule units of forward substitution */
+  int64_t nsupernodes_U;   /* schedule units of backward substitution */
+  int64_t nsn_levels_L;    /* dependent steps of the forward schedule */
+  int64_t nsn_levels_U;    /* dependent steps of the backward schedule */
+  int dtype;               /* icpcg_dtype of application */
+} icpcg_prec_info;
+
+icpcg_status icpcg_prec_get_info(icpcg_ctx *ctx, const icpcg_prec *P, icpcg_prec_info *info);
+
+/* Row level sets (supplementary section 5: substitution is sequential row
+ * by row; rows of one level are independent). level_L[i] = 0 if row i of L
+ * has no off-diagonal entry, else 1 + max level_L[j] over stored j < i;
+ * level_U likewise on L^T. perm_* lists rows sorted by (level, row);
+ * level_ptr_*[l] .. level_ptr_*[l+1] delimits level l. All outputs are
+ * device int32 buffers: level and perm sized n, level_ptr sized nlevels + 1
+ * (nlevels from icpcg_prec_get_info). Any pointer may be NULL. */
+icpcg_status icpcg_prec_levels(icpcg_ctx *ctx, const icpcg_prec *P, int32_t *level_L,
+                               int32_t *perm_L, int32_t *level_ptr_L, int32_t *level_U,
+                               int32_t *perm_U, int32_t *level_ptr_U);
+
+/* L^T as CSR (diagonal first in each row): U_row_ptr[n+1], U_col[nnz],
+ * U_val[nnz] FP64 device buffers. */
+icpcg_status icpcg_prec_transpose(icpcg_ctx *ctx, const icpcg_prec *P, int64_t *U_row_ptr,
+                                  int32_t *U_col, double *U_val);
+
+/* ------------------------------------------------------------ kernels */
+
+/* W = A X for nrhs columns (supplementary Algorithm 1, w = A p). X, W are
+ * FP64 n x nrhs blocks. */
+icpcg_status icpcg_spmv(icpcg_ctx *ctx, const icpcg_csr *A, const double *X, double *W,
+                        int64_t nrhs);
+
+/* One triangular solve with the preconditioner's factor: transpose = 0
+ * solves L Y = R (forward substitution), 1 solves L^T Y = R (backward),
+ * Eq. (11) read as standard substitution. R and Y are n x nrhs blocks of
+ * FP64 (dtype F64 preconditioner) or FP32 (F32/BF16 preconditioner), except
+ * that the forward solve of a reduced-precision preconditioner takes FP64 R
+ * when r_is_f64 = 1 (rounded to FP32 on load). */
+icpcg_status icpcg_trsv(icpcg_ctx *ctx, const icpcg_prec *P, int transpose, const void *R,
+                        int r_is_f64, void *Y, int64_t nrhs);
+
+/* Preconditioner solve P Z = R, P = L L^T (supplementary Algorithm 1, the two
+ * triangle solves): Y = L^-1 R, Z = L^-T Y. Blocks are FP64 for an F64
+ * preconditioner and FP32 otherwise (R may be FP64 with r_is_f64 = 1). Y is
+ * kept for icpcg_apply_backward and may not be NULL. */
+icpcg_status icpcg_apply(icpcg_ctx *ctx, const icpcg_prec *P, const void *R, int r_is_f64,
+                         void *Y, void *Z, int64_t nrhs);
+
+/* Reverse-mode derivative of Z = L^-T L^-1 R (not in the paper; what training
+ * a learned correction of L needs). Given G = dl/dZ and the Y, Z of the
+ * forward call: Ybar = L^-1 G, dR = L^-T Ybar, and for every stored (a, b) of
+ * L: dL_val[q] = -sum_k (Z_ak Ybar_bk + dR_ak Y_bk), in L's CSR order. Types
+ * follow icpcg_apply (FP64 or FP32 blocks, dL in the same type). Ybar is a
+ * caller scratch block of the same shape. */
+icpcg_status icpcg_apply_backward(icpcg_ctx *ctx, const icpcg_prec *P, const void *G,
+                                  const void *Y, const void *Z, void *Ybar, void *dR,
+                                  void *dL_val, int64_t nrhs);
+
+/* ----------------------------------------------------------------- PCG */
+
+typedef struct {
+  double rtol;           /* stop when ||r_k|| <= rtol ||b|| (per column) */
+  int64_t max_iter;      /* products A p per column; <= 0: min(n, max(10, 10 sqrt n)) */
+  int max_replace;       /* true-residual replacements per column (default 3 when < 0) */
+  int block_width;       /* columns per pass: 0 = autotune, else 1, 2, 4, 8 or 16 */
+  int check_every;       /* host polls the convergence flags every k steps (<= 0: 1) */
+  int use_graph;         /* 1: replay the captured step as a hipGraph */
+} icpcg_solve_opts;
+
+typedef struct {
+  int64_t iters;         /* products A p performed for this column */
+  int replacements;      /* residual replacements performed */
+  int status;            /* icpcg_status of this column */
+  double relres;         /* recurrence ||r|| / ||b|| at exit */
+  double true_relres;    /* ||b - A x|| / ||b|| at exit (FP64) */
+} icpcg_col_info;
+
+/* PCG of supplementary Algorithm 1 for nrhs right-hand sides at once
+ * (columns advance in lockstep and freeze when they converge; each column is
+ * the same iteration as a one-column solve). B is FP64 n x nrhs; X holds x_0
+ * on entry and the solution on exit. The stop test is the relative
+ * recurrence residual, then the true residual b - A x is checked and, when it
+ * is above the tolerance, r is replaced by it and the iteration continues
+ * (at most max_replace times). Iterations count the products A p; b = 0
+ * gives x = 0 after 0 iterations. info (nullable) receives nrhs entries.
+ * Returns the worst column status. opts may be NULL (rtol 1e-8). */
+icpcg_status icpcg_solve(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P,
+                         const double *B, double *X, int64_t nrhs, const icpcg_solve_opts *opts,
+                         icpcg_col_info *info);
+
+/* Synchronize the context's stream and report a device-side failure of the
+ * non-synchronizing calls (a dependency wait that hit its time limit). */
+icpcg_status icpcg_sync(icpcg_ctx *ctx);
+
+/* Library description (static string). */
+const char *icpcg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ICPCG_H */

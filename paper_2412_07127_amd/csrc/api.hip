@@ -1,0 +1,558 @@
+// C ABI entry points (include/icpcg.h): argument checks, object lifetime, the
+// IC(0) shift loop and the PCG driver. Every numerical step runs in the
+// library's own kernels; the host only sequences launches and reads the
+// per-column flags.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace icpcg {
+
+namespace {
+thread_local std::string g_err;
+
+__global__ void k_row_len(const int64_t *rp, int64_t n, int32_t *len) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    len[i] = (int32_t)(rp[i + 1] - rp[i]);
+}
+__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+const std::string &get_error() { return g_err; }
+
+}  // namespace icpcg
+
+using namespace icpcg;
+
+namespace {
+
+constexpr int kSmax = kSupernodeMax;
+
+icpcg_status finish(icpcg_ctx *ctx, int st) {
+  if (ctx && st != ICPCG_OK) ctx->last_error = get_error();
+  return (icpcg_status)st;
+}
+
+icpcg_status fail(icpcg_ctx *ctx, icpcg_status st, const std::string &msg) {
+  set_error(msg);
+  return finish(ctx, st);
+}
+
+bool valid_csr_args(const icpcg_csr *A) {
+  return A && A->n >= 0 && A->nnz >= 0 && A->n < INT32_MAX && (A->n == 0 || (A->row_ptr && A->col && A->val));
+}
+
+bool pow2_width(int64_t r) { return r == 1 || r == 2 || r == 4 || r == 8 || r == 16; }
+
+int64_t default_max_iter(int64_t n) {
+  int64_t m = (int64_t)(10.0 * std::sqrt((double)n));
+  if (m < 10) m = 10;
+  if (m > n) m = n;
+  if (m < 1) m = 1;
+  return m;
+}
+
+int check_matrix(icpcg_ctx *ctx, const icpcg_csr *A, int mode) {
+  if (A->n == 0) return ICPCG_OK;
+  int bad = -1;
+  int st = check_csr(A->row_ptr, A->col, A->n, A->nnz, mode, A->val, ctx->stream, &bad);
+  if (st) return st;
+  if (bad >= 0) {
+    set_error(std::string(mode == 1 ? "factor" : "matrix") + " row " + std::to_string(bad) +
+              (mode == 1 ? " is not lower triangular with a positive finite diagonal last, sorted columns, "
+                           "in-range indices and finite values"
+                         : " has unsorted, duplicate or out-of-range columns, no diagonal, or a non-finite value"));
+    return ICPCG_E_INVALID;
+  }
+  return ICPCG_OK;
+}
+
+// Device-side error flag of the dependency waits (shared SolveFlags buffer).
+int ensure_flags(icpcg_ctx *ctx) {
+  Workspace &ws = ctx->ws;
+  if (!ws.flags.p) {
+    int st = ws.flags.reserve(sizeof(SolveFlags) + 64);
+    if (st) return st;
+    ICPCG_HIP_TRY(hipMemsetAsync(ws.flags.p, 0, sizeof(SolveFlags) + 64, ctx->stream));
+  }
+  if (!ws.host_flags) ICPCG_HIP_TRY(hipHostMalloc(&ws.host_flags, sizeof(SolveFlags) + 64, hipHostMallocDefault));
+  return ICPCG_OK;
+}
+
+SolveFlags *dev_flags(icpcg_ctx *ctx) { return ctx->ws.flags.as<SolveFlags>(); }
+unsigned *dev_counter(icpcg_ctx *ctx) {
+  return reinterpret_cast<unsigned *>(ctx->ws.flags.as<char>() + sizeof(SolveFlags));
+}
+
+int read_flags(icpcg_ctx *ctx, SolveFlags *h) {
+  ICPCG_HIP_TRY(hipMemcpyAsync(ctx->ws.host_flags, ctx->ws.flags.p, sizeof(SolveFlags), hipMemcpyDeviceToHost,
+                               ctx->stream));
+  ICPCG_HIP_TRY(hipStreamSynchronize(ctx->stream));
+  std::memcpy(h, ctx->ws.host_flags, sizeof(SolveFlags));
+  return ICPCG_OK;
+}
+
+int take_wait_error(icpcg_ctx *ctx) {
+  SolveFlags h;
+  int st = read_flags(ctx, &h);
+  if (st) return st;
+  if (h.err) {
+    ICPCG_HIP_TRY(hipMemsetAsync(&dev_flags(ctx)->err, 0, sizeof(int), ctx->stream));
+    set_error("a device-side dependency wait exceeded its time limit");
+    return ICPCG_E_DEVICE;
+  }
+  return ICPCG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *icpcg_version(void) {
+  return "icpcg 0.1 (gfx950; IC(0)-PCG with sync-free supernodal triangular solves)";
+}
+
+const char *icpcg_status_string(icpcg_status st) {
+  switch (st) {
+    case ICPCG_OK: return "ok";
+    case ICPCG_E_INVALID: return "invalid argument";
+    case ICPCG_E_PIVOT: return "IC(0) pivot breakdown";
+    case ICPCG_E_BREAKDOWN: return "PCG breakdown";
+    case ICPCG_E_MAXITER: return "maximum iterations reached";
+    case ICPCG_E_NONFINITE: return "non-finite value";
+    case ICPCG_E_DEVICE: return "device error";
+    case ICPCG_E_NOMEM: return "out of device memory";
+    case ICPCG_E_TRUE_RESIDUAL: return "true residual above tolerance";
+  }
+  return "unknown status";
+}
+
+icpcg_status icpcg_create(icpcg_ctx **out, void *stream) {
+  if (!out) return ICPCG_E_INVALID;
+  *out = nullptr;
+  icpcg_ctx *ctx = new (std::nothrow) icpcg_ctx();
+  if (!ctx) return ICPCG_E_NOMEM;
+  ctx->stream = (hipStream_t)stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    delete ctx;
+    return ICPCG_E_DEVICE;
+  }
+  ctx->dev.id = dev;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+    ctx->dev.num_cu = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0)
+    ctx->dev.wall_hz = (long long)v * 1000LL;  // attribute is in kHz
+  ctx->dev.wait_ticks = ctx->dev.wall_hz * 4;  // 4 s
+  if (ensure_flags(ctx) != ICPCG_OK) {
+    delete ctx;
+    return ICPCG_E_NOMEM;
+  }
+  *out = ctx;
+  return ICPCG_OK;
+}
+
+icpcg_status icpcg_destroy(icpcg_ctx *ctx) {
+  if (!ctx) return ICPCG_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws.host_flags) (void)hipHostFree(ctx->ws.host_flags);
+  delete ctx;
+  return ICPCG_OK;
+}
+
+icpcg_status icpcg_set_stream(icpcg_ctx *ctx, void *stream) {
+  if (!ctx) return ICPCG_E_INVALID;
+  ctx->stream = (hipStream_t)stream;
+  return ICPCG_OK;
+}
+
+const char *icpcg_last_error(const icpcg_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+icpcg_status icpcg_tril_nnz(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *nnz_lower) {
+  if (!ctx || !valid_csr_args(A) || !nnz_lower) return fail(ctx, ICPCG_E_INVALID, "tril_nnz: bad arguments");
+  if (A->n == 0) { *nnz_lower = 0; return ICPCG_OK; }
+  int st = check_matrix(ctx, A, 0);
+  if (st) return finish(ctx, st);
+  DevBuf cnt, ex;
+  if (cnt.reserve(A->n * 8) || ex.reserve(A->n * 8)) return finish(ctx, ICPCG_E_NOMEM);
+  if ((st = tril_count(A->row_ptr, A->col, A->n, cnt.as<int64_t>(), ctx->stream))) return finish(ctx, st);
+  int64_t total = 0;
+  if ((st = scan_exclusive_i64(cnt.as<int64_t>(), ex.as<int64_t>(), A->n, ctx->stream, &total)))
+    return finish(ctx, st);
+  *nnz_lower = total;
+  return ICPCG_OK;
+}
+
+icpcg_status icpcg_factor(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *L_row_ptr, int32_t *L_col, double *L_val,
+                          const icpcg_factor_opts *opts, icpcg_factor_info *info) {
+  if (!ctx || !valid_csr_args(A) || (A->n > 0 && (!L_row_ptr || !L_col || !L_val)))
+    return fail(ctx, ICPCG_E_INVALID, "factor: bad arguments");
+  const int64_t n = A->n;
+  const int max_restarts = opts && opts->max_restarts >= 0 ? opts->max_restarts : 30;
+  const double alpha_min = opts && opts->alpha_min > 0 ? opts->alpha_min : 1e-3;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (n == 0) return ICPCG_OK;
+  hipStream_t s = ctx->stream;
+  int st = check_matrix(ctx, A, 0);
+  if (st) return finish(ctx, st);
+  // pattern of tril(A)
+  DevBuf cnt;
+  if (cnt.reserve(n * 8)) return finish(ctx, ICPCG_E_NOMEM);
+  if ((st = tril_count(A->row_ptr, A->col, n, cnt.as<int64_t>(), s))) return finish(ctx, st);
+  int64_t nnzl = 0;
+  if ((st = scan_exclusive_i64(cnt.as<int64_t>(), L_row_ptr, n, s, &nnzl))) return finish(ctx, st);
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, L_row_ptr + n, nnzl);
+  DevBuf a_low, pivots, lens, perm, lptr, fl;
+  if (a_low.reserve(nnzl * 8) || pivots.reserve(n * 8) || lens.reserve(n * 4) || perm.reserve(n * 4) ||
+      lptr.reserve((n + 1) * 4) || fl.reserve(4))
+    return finish(ctx, ICPCG_E_NOMEM);
+  if ((st = tril_copy(A->row_ptr, A->col, A->val, n, L_row_ptr, L_col, a_low.as<double>(), s))) return finish(ctx, st);
+  // longest row (LDS staging limit)
+  hipLaunchKernelGGL(k_row_len, dim3(1024), dim3(256), 0, s, L_row_ptr, n, lens.as<int32_t>());
+  int32_t maxlen = 0;
+  if ((st = reduce_max_i32(lens.as<int32_t>(), n, s, &maxlen))) return finish(ctx, st);
+  if (maxlen > ic0_max_row())
+    return fail(ctx, ICPCG_E_INVALID, "factor: a row of tril(A) has " + std::to_string(maxlen) +
+                                          " entries (limit " + std::to_string(ic0_max_row()) + ")");
+  // row levels of tril(A)
+  int64_t nlev = 0;
+  if ((st = row_levels(L_row_ptr, L_col, n, false, nullptr, perm.as<int32_t>(), lptr.as<int32_t>(), &nlev, s,
+                       ctx->dev)))
+    return finish(ctx, st);
+  std::vector<int32_t> hlp((size_t)nlev + 1);
+  if (hipMemcpyAsync(hlp.data(), lptr.p, (nlev + 1) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(ctx, ICPCG_E_DEVICE, "factor: level copy failed");
+  double alpha = 0.0;
+  int restarts = 0;
+  int ok = 0;
+  for (restarts = 0; restarts <= max_restarts; ++restarts) {
+    if (restarts > 0) alpha = std::max(alpha_min, 2.0 * alpha);
+    if ((st = fill_i32(fl.as<int32_t>(), 0, 1, s))) return finish(ctx, st);
+    if ((st = ic0_factor_levels(L_row_ptr, L_col, L_val, a_low.as<double>(), n, perm.as<int32_t>(), hlp, alpha,
+                                fl.as<int>(), pivots.as<double>(), s, maxlen)))
+      return finish(ctx, st);
+    int hfail = 0;
+    if (hipMemcpyAsync(&hfail, fl.p, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return fail(ctx, ICPCG_E_DEVICE, "factor: flag copy failed");
+    if (!hfail) { ok = 1; break; }
+  }
+  if (restarts > max_restarts) restarts = max_restarts;
+  double minp = 0.0;
+  if ((st = reduce_min_f64(pivots.as<double>(), n, s, &minp))) return finish(ctx, st);
+  if (info) {
+    info->alpha = alpha;
+    info->restarts = restarts;
+    info->min_pivot = minp;
+    info->nlevels = nlev;
+  }
+  if (!ok) return fail(ctx, ICPCG_E_PIVOT, "factor: IC(0) broke down for every shift tried");
+  return ICPCG_OK;
+}
+
+icpcg_status icpcg_prec_create(icpcg_ctx *ctx, const icpcg_csr *L, icpcg_dtype dt, icpcg_prec **out) {
+  if (!ctx || !valid_csr_args(L) || !out || (dt != ICPCG_F64 && dt != ICPCG_F32 && dt != ICPCG_BF16) || L->n == 0)
+    return fail(ctx, ICPCG_E_INVALID, "prec_create: bad arguments");
+  *out = nullptr;
+  hipStream_t s = ctx->stream;
+  int st = check_matrix(ctx, L, 1);
+  if (st) return finish(ctx, st);
+  icpcg_prec *P = new (std::nothrow) icpcg_prec();
+  if (!P) return finish(ctx, ICPCG_E_NOMEM);
+  P->n = L->n;
+  P->nnz = L->nnz;
+  P->dtype = dt;
+  auto bail = [&](int code) { delete P; return finish(ctx, code); };
+  if (P->lrp.reserve((P->n + 1) * 8) || P->lci.reserve(P->nnz * 4) || P->lval.reserve(P->nnz * 8))
+    return bail(ICPCG_E_NOMEM);
+  if (hipMemcpyAsync(P->lrp.p, L->row_ptr, (P->n + 1) * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(P->lci.p, L->col, P->nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(P->lval.p, L->val, P->nnz * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return bail(host_error(hipGetLastError(), "copy factor", __FILE__, __LINE__));
+  if ((st = build_transpose(P, s))) return bail(st);
+  if ((st = build_schedule(P->lrp.as<int64_t>(), P->lci.as<int32_t>(), P->n, false, kSmax, P->sl, s, ctx->dev)))
+    return bail(st);
+  if ((st = build_schedule(P->urp.as<int64_t>(), P->uci.as<int32_t>(), P->n, true, kSmax, P->su, s, ctx->dev)))
+    return bail(st);
+  if (hipStreamSynchronize(s) != hipSuccess) return bail(host_error(hipGetLastError(), "sync", __FILE__, __LINE__));
+  *out = P;
+  return ICPCG_OK;
+}
+
+icpcg_status icpcg_prec_destroy(icpcg_prec *P) {
+  delete P;
+  return ICPCG_OK;
+}
+
+icpcg_status icpcg_prec_update_values(icpcg_ctx *ctx, icpcg_prec *P, const double *L_val) {
+  if (!ctx || !P || !L_val) return fail(ctx, ICPCG_E_INVALID, "prec_update_values: bad arguments");
+  icpcg_csr L{P->n, P->nnz, P->lrp.as<int64_t>(), P->lci.as<int32_t>(), L_val};
+  int st = check_matrix(ctx, &L, 1);
+  if (st) return finish(ctx, st);
+  if (hipMemcpyAsync(P->lval.p, L_val, P->nnz * 8, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+    return finish(ctx, host_error(hipGetLastError(), "copy values", __FILE__, __LINE__));
+  return finish(ctx, refresh_values(P, ctx->stream));
+}
+
+icpcg_status icpcg_prec_get_info(icpcg_ctx *ctx, const icpcg_prec *Pc, icpcg_prec_info *info) {
+  if (!ctx || !Pc || !info) return fail(ctx, ICPCG_E_INVALID, "prec_get_info: bad arguments");
+  icpcg_prec *P = const_cast<icpcg_prec *>(Pc);
+  int st;
+  if (P->nlev_rows_L < 0) {
+    if ((st = row_levels(P->lrp.as<int64_t>(), P->lci.as<int32_t>(), P->n, false, nullptr, nullptr, nullptr,
+                         &P->nlev_rows_L, ctx->stream, ctx->dev)))
+      return finish(ctx, st);
+  }
+  if (P->nlev_rows_U < 0) {
+    if ((st = row_levels(P->urp.as<int64_t>(), P->uci.as<int32_t>(), P->n, true, nullptr, nullptr, nullptr,
+                         &P->nlev_rows_U, ctx->stream, ctx->dev)))
+      return finish(ctx, st);
+  }
+  info->n = P->n;
+  info->nnz = P->nnz;
+  info->nlevels_L = P->nlev_rows_L;
+  info->nlevels_U = P->nlev_rows_U;
+  info->nsupernodes_L = P->sl.nsn;
+  info->nsupernodes_U = P->su.nsn;
+  info->nsn_levels_L = P->sl.nlev;
+  info->nsn_levels_U = P->su.nlev;
+  info->dtype = (int)P->dtype;
+  return ICPCG_OK;
+}
+
+icpcg_status icpcg_prec_levels(icpcg_ctx *ctx, const icpcg_prec *Pc, int32_t *level_L, int32_t *perm_L,
+                               int32_t *level_ptr_L, int32_t *level_U, int32_t *perm_U, int32_t *level_ptr_U) {
+  if (!ctx || !Pc) return fail(ctx, ICPCG_E_INVALID, "prec_levels: bad arguments");
+  icpcg_prec *P = const_cast<icpcg_prec *>(Pc);
+  int st;
+  if (level_L || perm_L || level_ptr_L) {
+    if ((st = row_levels(P->lrp.as<int64_t>(), P->lci.as<int32_t>(), P->n, false, level_L, perm_L, level_ptr_L,
+                         &P->nlev_rows_L, ctx->stream, ctx->dev)))
+      return finish(ctx, st);
+  }
+  if (level_U || perm_U || level_ptr_U) {
+    if ((st = row_levels(P->urp.as<int64_t>(), P->uci.as<int32_t>(), P->n, true, level_U, perm_U, level_ptr_U,
+                         &P->nlev_rows_U, ctx->stream, ctx->dev)))
+      return finish(ctx, st);
+  }
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return finish(ctx, host_error(hipGetLastError(), "sync", __FILE__, __LINE__));
+  return ICPCG_OK;
+}
+
+icpcg_status icpcg_prec_transpose(icpcg_ctx *ctx, const icpcg_prec *P, int64_t *urp, int32_t *uci, double *uval) {
+  if (!ctx || !P) return fail(ctx, ICPCG_E_INVALID, "prec_transpose: bad arguments");
+  hipStream_t s = ctx->stream;
+  if ((urp && hipMemcpyAsync(urp, P->urp.p, (P->n + 1) * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
+      (uci && hipMemcpyAsync(uci, P->uci.p, P->nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
+      (uval && hipMemcpyAsync(uval, P->uval.p, P->nnz * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return finish(ctx, host_error(hipGetLastError(), "copy transpose", __FILE__, __LINE__));
+  return ICPCG_OK;
+}
+
+icpcg_status icpcg_spmv(icpcg_ctx *ctx, const icpcg_csr *A, const double *X, double *W, int64_t nrhs) {
+  if (!ctx || !valid_csr_args(A) || !pow2_width(nrhs) || (A->n > 0 && (!X || !W)))
+    return fail(ctx, ICPCG_E_INVALID, "spmv: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
+  return finish(ctx, spmv(A->row_ptr, A->col, A->val, A->n, X, W, (int)nrhs, spmv_default_slots((int)nrhs),
+                          ctx->stream, nullptr, nullptr, nullptr, 0, 0));
+}
+
+icpcg_status icpcg_trsv(icpcg_ctx *ctx, const icpcg_prec *P, int transpose, const void *R, int r_is_f64, void *Y,
+                        int64_t nrhs) {
+  if (!ctx || !P || !R || !Y || !pow2_width(nrhs))
+    return fail(ctx, ICPCG_E_INVALID, "trsv: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
+  const bool lo = P->dtype != ICPCG_F64;
+  int st = fill_pending(Y, P->n * nrhs, lo, ctx->stream);
+  if (st) return finish(ctx, st);
+  return finish(ctx, trsv(P, transpose != 0, R, lo ? r_is_f64 != 0 : true, Y, (int)nrhs, nrhs, ctx->stream, ctx->dev,
+                          &dev_flags(ctx)->err));
+}
+
+icpcg_status icpcg_apply(icpcg_ctx *ctx, const icpcg_prec *P, const void *R, int r_is_f64, void *Y, void *Z,
+                         int64_t nrhs) {
+  if (!ctx || !P || !R || !Y || !Z || !pow2_width(nrhs))
+    return fail(ctx, ICPCG_E_INVALID, "apply: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
+  const bool lo = P->dtype != ICPCG_F64;
+  hipStream_t s = ctx->stream;
+  int st;
+  if ((st = fill_pending(Y, P->n * nrhs, lo, s))) return finish(ctx, st);
+  if ((st = trsv(P, false, R, lo ? r_is_f64 != 0 : true, Y, (int)nrhs, nrhs, s, ctx->dev, &dev_flags(ctx)->err)))
+    return finish(ctx, st);
+  if ((st = fill_pending(Z, P->n * nrhs, lo, s))) return finish(ctx, st);
+  return finish(ctx, trsv(P, true, Y, !lo, Z, (int)nrhs, nrhs, s, ctx->dev, &dev_flags(ctx)->err));
+}
+
+icpcg_status icpcg_apply_backward(icpcg_ctx *ctx, const icpcg_prec *P, const void *G, const void *Y, const void *Z,
+                                  void *Ybar, void *dR, void *dL, int64_t nrhs) {
+  if (!ctx || !P || !G || !Y || !Z || !Ybar || !dR || !dL || !pow2_width(nrhs))
+    return fail(ctx, ICPCG_E_INVALID, "apply_backward: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
+  const bool lo = P->dtype != ICPCG_F64;
+  hipStream_t s = ctx->stream;
+  int st;
+  if ((st = fill_pending(Ybar, P->n * nrhs, lo, s))) return finish(ctx, st);
+  if ((st = trsv(P, false, G, !lo, Ybar, (int)nrhs, nrhs, s, ctx->dev, &dev_flags(ctx)->err))) return finish(ctx, st);
+  if ((st = fill_pending(dR, P->n * nrhs, lo, s))) return finish(ctx, st);
+  if ((st = trsv(P, true, Ybar, !lo, dR, (int)nrhs, nrhs, s, ctx->dev, &dev_flags(ctx)->err))) return finish(ctx, st);
+  return finish(ctx, prec_dL(P, Z, Ybar, dR, Y, dL, (int)nrhs, s));
+}
+
+icpcg_status icpcg_sync(icpcg_ctx *ctx) {
+  if (!ctx) return ICPCG_E_INVALID;
+  return finish(ctx, take_wait_error(ctx));
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ PCG
+
+namespace {
+
+struct PassBuffers {
+  double *r, *p, *w, *B, *X;
+  void *y, *z;
+  double *partials;
+  ColState *cols;
+};
+
+// One block of R columns through supplementary Algorithm 1 with the stop,
+// replacement and failure rules stated in icpcg.h.
+int run_pass(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const PassBuffers &b, int R,
+             const icpcg_solve_opts &o, int64_t max_iter) {
+  hipStream_t s = ctx->stream;
+  const int64_t n = A->n;
+  const bool lo = P->dtype != ICPCG_F64;
+  const int slots = spmv_default_slots(R);
+  SolveFlags *fl = dev_flags(ctx);
+  unsigned *ctr = dev_counter(ctx);
+  int *err = &fl->err;
+  int st;
+  ICPCG_HIP_TRY(hipMemsetAsync(fl, 0, sizeof(SolveFlags), s));
+  ICPCG_HIP_TRY(hipMemsetAsync(ctr, 0, sizeof(unsigned), s));
+  if ((st = spmv(A->row_ptr, A->col, A->val, n, b.X, b.w, R, slots, s, nullptr, nullptr, nullptr, 0, 0))) return st;
+  if ((st = pcg_init(n, R, b.B, b.w, b.r, b.p, b.y, b.z, lo, o.rtol, b.partials, ctr, b.cols, max_iter, o.max_replace,
+                     fl, s)))
+    return st;
+  if ((st = pcg_zero_x(n, R, b.X, b.cols, s))) return st;
+  const int every = o.check_every > 0 ? o.check_every : 1;
+  const int64_t guard = max_iter * (int64_t)(o.max_replace + 1) + 16;
+  int64_t steps = 0;
+  for (;;) {
+    SolveFlags h;
+    if ((st = read_flags(ctx, &h))) return st;
+    if (h.err) {
+      set_error("a device-side dependency wait exceeded its time limit");
+      return ICPCG_E_DEVICE;
+    }
+    if (h.n_active == 0) {
+      if (h.n_conv == 0) break;
+      if ((st = spmv(A->row_ptr, A->col, A->val, n, b.X, b.w, R, slots, s, nullptr, nullptr, nullptr, 0, 0))) return st;
+      if ((st = pcg_true_residual(n, R, b.B, b.w, b.partials, ctr, b.cols, max_iter, o.max_replace, 0, fl, s)))
+        return st;
+      if ((st = pcg_replace_r(n, R, b.w, b.r, b.cols, s))) return st;
+      continue;
+    }
+    if (steps > guard) {
+      set_error("solve: step guard exceeded");
+      return ICPCG_E_DEVICE;
+    }
+    for (int k = 0; k < every; ++k, ++steps) {
+      if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err))) return st;
+      if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err))) return st;
+      if ((st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, ctr, b.cols, fl, s))) return st;
+      if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.z, b.cols, s))) return st;
+      if ((st = spmv(A->row_ptr, A->col, A->val, n, b.p, b.w, R, slots, s, b.partials, ctr, b.cols, max_iter, 1)))
+        return st;
+      if ((st = pcg_update_xr(n, R, b.X, b.r, b.p, b.w, b.partials, ctr, b.cols, max_iter, fl, s))) return st;
+    }
+  }
+  // final true residual of every column (reported)
+  if ((st = spmv(A->row_ptr, A->col, A->val, n, b.X, b.w, R, slots, s, nullptr, nullptr, nullptr, 0, 0))) return st;
+  if ((st = pcg_true_residual(n, R, b.B, b.w, b.partials, ctr, b.cols, max_iter, o.max_replace, 1, fl, s))) return st;
+  return ICPCG_OK;
+}
+
+}  // namespace
+
+extern "C" icpcg_status icpcg_solve(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const double *B,
+                                    double *X, int64_t nrhs, const icpcg_solve_opts *opts, icpcg_col_info *info) {
+  if (!ctx || !valid_csr_args(A) || !P || nrhs < 1 || A->n != P->n || (A->n > 0 && (!B || !X)))
+    return fail(ctx, ICPCG_E_INVALID, "solve: bad arguments");
+  icpcg_solve_opts o{1e-8, 0, 3, 0, 1, 0};
+  if (opts) o = *opts;
+  if (!(o.rtol >= 0.0)) return fail(ctx, ICPCG_E_INVALID, "solve: rtol must be >= 0");
+  if (o.max_replace < 0) o.max_replace = 3;
+  const int64_t n = A->n;
+  const int64_t max_iter = o.max_iter > 0 ? o.max_iter : default_max_iter(n);
+  if (n == 0) {
+    if (info)
+      for (int64_t c = 0; c < nrhs; ++c) info[c] = icpcg_col_info{0, 0, ICPCG_OK, 0.0, 0.0};
+    return ICPCG_OK;
+  }
+  int Rb = o.block_width;
+  if (Rb == 0) {
+    Rb = 1;
+    while (Rb < nrhs && Rb < 16) Rb <<= 1;
+  }
+  if (!pow2_width(Rb)) return fail(ctx, ICPCG_E_INVALID, "solve: block_width must be 0, 1, 2, 4, 8 or 16");
+  const bool lo = P->dtype != ICPCG_F64;
+  hipStream_t s = ctx->stream;
+  Workspace &ws = ctx->ws;
+  const size_t vec8 = (size_t)n * Rb * 8, vecy = (size_t)n * Rb * (lo ? 4 : 8);
+  const bool gathered = nrhs != Rb;
+  if (ws.r.reserve(vec8) || ws.p.reserve(vec8) || ws.w.reserve(vec8) || ws.y.reserve(vecy) || ws.z.reserve(vecy) ||
+      ws.partials.reserve((size_t)4096 * Rb * 2 * 8) || ws.cols.reserve(sizeof(ColState) * Rb))
+    return finish(ctx, ICPCG_E_NOMEM);
+  if (gathered && (ws.tmp0.reserve(vec8) || ws.tmp1.reserve(vec8))) return finish(ctx, ICPCG_E_NOMEM);
+  int worst = ICPCG_OK;
+  std::vector<ColState> hc(Rb);
+  for (int64_t c0 = 0; c0 < nrhs; c0 += Rb) {
+    const int nc = (int)std::min<int64_t>(Rb, nrhs - c0);
+    PassBuffers b;
+    b.r = ws.r.as<double>();
+    b.p = ws.p.as<double>();
+    b.w = ws.w.as<double>();
+    b.y = ws.y.p;
+    b.z = ws.z.p;
+    b.partials = ws.partials.as<double>();
+    b.cols = ws.cols.as<ColState>();
+    int st;
+    if (gathered) {
+      b.B = ws.tmp0.as<double>();
+      b.X = ws.tmp1.as<double>();
+      if ((st = gather_cols(n, Rb, B, nrhs, c0, nc, b.B, s)) || (st = gather_cols(n, Rb, X, nrhs, c0, nc, b.X, s)))
+        return finish(ctx, st);
+    } else {
+      b.B = const_cast<double *>(B);
+      b.X = X;
+    }
+    if ((st = run_pass(ctx, A, P, b, Rb, o, max_iter))) return finish(ctx, st);
+    if (gathered && (st = scatter_cols(n, Rb, b.X, X, nrhs, c0, nc, s))) return finish(ctx, st);
+    if (hipMemcpyAsync(hc.data(), b.cols, sizeof(ColState) * Rb, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return finish(ctx, host_error(hipGetLastError(), "copy column states", __FILE__, __LINE__));
+    for (int c = 0; c < nc; ++c) {
+      const ColState &cs = hc[c];
+      if (info) {
+        info[c0 + c].iters = cs.iters;
+        info[c0 + c].replacements = cs.repl;
+        info[c0 + c].status = cs.status;
+        info[c0 + c].relres = cs.bb > 0 ? std::sqrt(cs.rr / cs.bb) : 0.0;
+        info[c0 + c].true_relres = cs.bb > 0 ? std::sqrt(cs.trr / cs.bb) : 0.0;
+      }
+      if (cs.status > worst) worst = cs.status;
+    }
+  }
+  if (worst != ICPCG_OK) {
+    set_error(std::string("solve: at least one column ended with status '") +
+              icpcg_status_string((icpcg_status)worst) + "'");
+    return finish(ctx, worst);
+  }
+  return ICPCG_OK;
+}

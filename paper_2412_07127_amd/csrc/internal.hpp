@@ -1,0 +1,186 @@
+// Host-side internals of the library: device buffers, the context and
+// preconditioner objects, and the launchers each translation unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/icpcg.h"
+#include "common.hpp"
+
+namespace icpcg {
+
+// Largest supernode (rows solved together by one wave) of the triangular
+// solve schedules.
+constexpr int kSupernodeMax = 4;
+
+// Last error text of the calling thread; the ABI layer copies it into the
+// context that made the call.
+void set_error(const std::string &msg);
+const std::string &get_error();
+
+// Owning device buffer (hipMalloc / hipFree).
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf &operator=(DevBuf &&o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // (Re)allocate to at least `b` bytes; returns ICPCG_OK or ICPCG_E_NOMEM.
+  int reserve(size_t b);
+  template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+struct Device {
+  int id = 0;
+  int num_cu = 256;
+  long long wall_hz = 100000000;  // wall_clock64 rate
+  long long wait_ticks = 400000000;  // device-side wait limit (4 s)
+};
+
+// Per-column PCG state kept on the device.
+struct ColState {
+  double bb, tol2, rr, rz, pw, alpha, beta, trr;
+  int active;   // still iterating
+  int conv;     // recurrence converged, true residual pending
+  int status;   // icpcg_status
+  int iters;    // products A p
+  int repl;     // residual replacements
+  int replace;  // replace r by the true residual on the next pass
+  int zero_x;   // b = 0: x is set to 0
+  int pad;
+};
+
+struct SolveFlags {
+  int n_active;
+  int n_conv;
+  int err;
+  int pad;
+};
+
+// Work buffers of a context (grow monotonically).
+struct Workspace {
+  DevBuf r, p, w, y, z, partials, cols, flags, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5;
+  void *host_flags = nullptr;  // pinned SolveFlags
+};
+
+}  // namespace icpcg
+
+struct icpcg_ctx {
+  hipStream_t stream = nullptr;
+  icpcg::Device dev;
+  icpcg::Workspace ws;
+  std::string last_error;
+  // cached autotune decisions keyed by (n, nnz, R)
+  struct Tune { int64_t n, nnz; int R; int spmv_slots; };
+  std::vector<Tune> tunes;
+};
+
+// One triangular factor's schedule: supernodes (row ranges solved together)
+// ordered by level.
+struct TriSchedule {
+  icpcg::DevBuf sn_ptr;    // int32[nsn + 1]
+  icpcg::DevBuf sn_order;  // int32[nsn]: supernodes sorted by (level, id)
+  int64_t nsn = 0;
+  int64_t nlev = 0;
+};
+
+struct icpcg_prec {
+  int64_t n = 0, nnz = 0;
+  icpcg_dtype dtype = ICPCG_F64;
+  icpcg::DevBuf lrp, lci, lval;      // L (int64, int32, f64)
+  icpcg::DevBuf urp, uci, uval;      // U = L^T (int64, int32, f64)
+  icpcg::DevBuf upos;                // int32: L position of each U entry
+  icpcg::DevBuf lval_lo, uval_lo;    // f32 or bf16 copies
+  TriSchedule sl, su;                // forward / backward schedules
+  int64_t nlev_rows_L = -1, nlev_rows_U = -1;  // row level counts (on demand)
+};
+
+namespace icpcg {
+
+// ------------------------------------------------------------ primitives
+// All launchers enqueue on `s` and return an icpcg_status value.
+int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s, int64_t *total_host);
+int scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, int32_t *total_host);
+int scan_inclusive_max_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+int reduce_max_i32(const int32_t *in, int64_t n, hipStream_t s, int32_t *host_out);
+int reduce_min_f64(const double *in, int64_t n, hipStream_t s, double *host_out);
+// Stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
+// Inputs are preserved; sorted results land in keys_out / vals_out.
+int radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out,
+                     uint32_t *vals_out, int64_t n, int bits, hipStream_t s);
+int fill_iota_u32(uint32_t *out, int64_t n, hipStream_t s);
+int fill_i32(int32_t *out, int32_t v, int64_t n, hipStream_t s);
+int fill_u64(uint64_t *out, uint64_t v, int64_t n, hipStream_t s);
+int fill_u32(uint32_t *out, uint32_t v, int64_t n, hipStream_t s);
+
+// ------------------------------------------------------------ setup
+int check_csr(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nnz, int mode,
+              const double *val, hipStream_t s, int *bad_row_host);
+int tril_count(const int64_t *rp, const int32_t *ci, int64_t n, int64_t *cnt, hipStream_t s);
+int tril_copy(const int64_t *rp, const int32_t *ci, const double *v, int64_t n,
+              const int64_t *lrp, int32_t *lci, double *lv, hipStream_t s);
+int build_transpose(icpcg_prec *P, hipStream_t s);
+int refresh_values(icpcg_prec *P, hipStream_t s);
+int build_schedule(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int smax,
+                   TriSchedule &out, hipStream_t s, const Device &dev);
+int row_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int32_t *level,
+               int32_t *perm, int32_t *level_ptr, int64_t *nlev_host, hipStream_t s,
+               const Device &dev);
+
+// ------------------------------------------------------------ kernels
+int ic0_factor_levels(const int64_t *lrp, const int32_t *lci, double *lv, const double *a_lower,
+                      int64_t n, const int32_t *perm, const std::vector<int32_t> &level_ptr,
+                      double alpha, int *fail_flag, double *pivots, hipStream_t s, int max_row_len);
+int ic0_max_row();
+int spmv_default_slots(int R);
+
+int spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x,
+         double *y, int R, int slots, hipStream_t s,
+         // optional fused p.w reduction (nullptr: none)
+         double *partials, unsigned *counter, ColState *cols, int64_t max_iter, int mode);
+
+int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *out, int R,
+         int64_t ld, hipStream_t s, const Device &dev, int *err);
+
+int prec_dL(const icpcg_prec *P, const void *Z, const void *Yb, const void *Rb, const void *Y,
+            void *dL, int R, hipStream_t s);
+
+// PCG vector steps (vec.hip)
+enum ReduceMode { RED_NONE = 0, RED_PW = 1 };
+int pcg_init(int64_t n, int R, const double *B, const double *W, double *r, double *p,
+             void *y, void *z, bool f32, double rtol, double *partials, unsigned *counter,
+             ColState *cols, int64_t max_iter, int max_replace, SolveFlags *flags, hipStream_t s);
+int pcg_zero_x(int64_t n, int R, double *X, const ColState *cols, hipStream_t s);
+int pcg_dot_rz(int64_t n, int R, const double *r, const void *z, bool f32, double *partials,
+               unsigned *counter, ColState *cols, SolveFlags *flags, hipStream_t s);
+int pcg_update_p(int64_t n, int R, const void *z, bool f32, double *p, void *y, void *zf,
+                 const ColState *cols, hipStream_t s);
+int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const double *w,
+                  double *partials, unsigned *counter, ColState *cols, int64_t max_iter,
+                  SolveFlags *flags, hipStream_t s);
+int pcg_true_residual(int64_t n, int R, const double *B, double *W, double *partials,
+                      unsigned *counter, ColState *cols, int64_t max_iter, int max_replace,
+                      int final_pass, SolveFlags *flags, hipStream_t s);
+int pcg_replace_r(int64_t n, int R, const double *W, double *r, ColState *cols, hipStream_t s);
+int gather_cols(int64_t n, int R, const double *src, int64_t lds, int64_t c0, int nc, double *dst,
+                hipStream_t s);
+int scatter_cols(int64_t n, int R, const double *src, double *dst, int64_t ldd, int64_t c0, int nc,
+                 hipStream_t s);
+int fill_pending(void *p, int64_t count, bool f32, hipStream_t s);
+
+}  // namespace icpcg

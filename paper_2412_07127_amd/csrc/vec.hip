@@ -1,0 +1,368 @@
+// Vector steps of the PCG loop (supplementary Algorithm 1) for an R-column
+// block, each fused with the one grid-wide reduction it needs and a per-column
+// finalizer that runs in the last block:
+//   init          r = b - A x0, ||b||^2, ||r||^2           -> tolerance, start flags
+//   dot_rz        r^T z                                     -> beta = r_k^T z_k / r_{k-1}^T z_{k-1}
+//   update_p      p = z + beta p (also re-arms y, z as pending for the next solves)
+//   update_xr     x += alpha p, r -= alpha w, ||r||^2        -> iteration count, stop test
+//   true_residual b - A x, ||b - A x||^2                     -> accept / replace / give up
+// Converged or failed columns are frozen (their x, r, p are no longer touched).
+#include "reduce.hpp"
+
+namespace icpcg {
+
+namespace {
+
+constexpr int kBlock = kRedBlock;
+
+inline unsigned vec_grid(int64_t n, int R) {
+  int64_t g = (n * R + kBlock - 1) / kBlock;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+#define ICPCG_GRID_LOOP(e, total) \
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < (total); e += (int64_t)gridDim.x * kBlock)
+
+template <typename T> struct Pending;
+template <> struct Pending<double> {
+  static __device__ __forceinline__ double get() { return bitcast<double>(Flag<double>::kPending); }
+};
+template <> struct Pending<float> {
+  static __device__ __forceinline__ float get() { return bitcast<float>(Flag<float>::kPending); }
+};
+
+template <int R, typename TZ>
+__global__ __launch_bounds__(kBlock) void k_init(int64_t n, const double *__restrict__ B, const double *__restrict__ W,
+                                                 double *__restrict__ r, double *__restrict__ p, TZ *__restrict__ y,
+                                                 TZ *__restrict__ z, double rtol, double *partials, unsigned *counter,
+                                                 ColState *cols, int64_t max_iter, SolveFlags *flags) {
+  __shared__ double smem[2 * kRedBlock];
+  __shared__ double out[2 * R];
+  double bb = 0.0, rr = 0.0;
+  ICPCG_GRID_LOOP(e, n * R) {
+    const double b = B[e];
+    const double ri = b - W[e];
+    r[e] = ri;
+    p[e] = 0.0;
+    y[e] = Pending<TZ>::get();
+    z[e] = Pending<TZ>::get();
+    bb += b * b;
+    rr += ri * ri;
+  }
+  const double v[2] = {bb, rr};
+  if (grid_reduce<R, 2>(v, partials, counter, smem, out)) {
+    const int t = threadIdx.x;
+    if (t < R) {
+      ColState cs;
+      cs.bb = out[t];
+      cs.rr = out[R + t];
+      cs.tol2 = rtol * rtol * cs.bb;
+      cs.rz = cs.pw = cs.alpha = cs.beta = 0.0;
+      cs.trr = cs.rr;
+      cs.iters = cs.repl = cs.replace = cs.zero_x = 0;
+      cs.status = ICPCG_OK;
+      cs.conv = 0;
+      cs.active = 0;
+      cs.pad = 0;
+      if (cs.bb == 0.0) {
+        cs.zero_x = 1;  // b = 0: x = 0 after 0 iterations
+        cs.rr = cs.trr = 0.0;
+      } else if (!isfinite(cs.rr) || !isfinite(cs.bb)) {
+        cs.status = ICPCG_E_NONFINITE;
+      } else if (cs.rr <= cs.tol2) {
+        cs.conv = 1;
+      } else if (max_iter <= 0) {
+        cs.status = ICPCG_E_MAXITER;
+      } else {
+        cs.active = 1;
+      }
+      cols[t] = cs;
+    }
+    __syncthreads();
+    count_flags<R>(cols, flags);
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_zero_x(int64_t n, double *__restrict__ X, const ColState *__restrict__ cols) {
+  ICPCG_GRID_LOOP(e, n * R) {
+    if (cols[e % R].zero_x) X[e] = 0.0;
+  }
+}
+
+template <int R, typename TZ>
+__global__ __launch_bounds__(kBlock) void k_dot_rz(int64_t n, const double *__restrict__ r, const TZ *__restrict__ z,
+                                                   double *partials, unsigned *counter, ColState *cols,
+                                                   SolveFlags *flags) {
+  __shared__ double smem[kRedBlock];
+  __shared__ double out[R];
+  double acc = 0.0;
+  ICPCG_GRID_LOOP(e, n * R) acc += r[e] * (double)z[e];
+  const double v[1] = {acc};
+  if (grid_reduce<R, 1>(v, partials, counter, smem, out)) {
+    const int t = threadIdx.x;
+    if (t < R) {
+      ColState &cs = cols[t];
+      cs.replace = 0;
+      if (cs.active) {
+        const double rz = out[t];
+        if (!isfinite(rz)) { cs.status = ICPCG_E_NONFINITE; cs.active = 0; }
+        else if (!(rz > 0.0)) { cs.status = ICPCG_E_BREAKDOWN; cs.active = 0; }
+        else {
+          cs.beta = cs.iters == 0 ? 0.0 : rz / cs.rz;
+          cs.rz = rz;
+        }
+      }
+    }
+    __syncthreads();
+    count_flags<R>(cols, flags);
+  }
+}
+
+template <int R, typename TZ>
+__global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, const TZ *__restrict__ z, double *__restrict__ p,
+                                                     TZ *__restrict__ y, TZ *__restrict__ zf,
+                                                     const ColState *__restrict__ cols) {
+  __shared__ double beta[R];
+  __shared__ int act[R];
+  if (threadIdx.x < R) {
+    beta[threadIdx.x] = cols[threadIdx.x].beta;
+    act[threadIdx.x] = cols[threadIdx.x].active;
+  }
+  __syncthreads();
+  ICPCG_GRID_LOOP(e, n * R) {
+    const int c = (int)(e % R);
+    if (act[c]) p[e] = (double)z[e] + beta[c] * p[e];
+    y[e] = Pending<TZ>::get();
+    zf[e] = Pending<TZ>::get();
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_update_xr(int64_t n, double *__restrict__ X, double *__restrict__ r,
+                                                      const double *__restrict__ p, const double *__restrict__ w,
+                                                      double *partials, unsigned *counter, ColState *cols,
+                                                      int64_t max_iter, SolveFlags *flags) {
+  __shared__ double smem[kRedBlock];
+  __shared__ double out[R];
+  __shared__ double alpha[R];
+  __shared__ int act[R];
+  if (threadIdx.x < R) {
+    alpha[threadIdx.x] = cols[threadIdx.x].alpha;
+    act[threadIdx.x] = cols[threadIdx.x].active;
+  }
+  __syncthreads();
+  double acc = 0.0;
+  ICPCG_GRID_LOOP(e, n * R) {
+    const int c = (int)(e % R);
+    if (act[c]) {
+      X[e] = X[e] + alpha[c] * p[e];
+      const double ri = r[e] - alpha[c] * w[e];
+      r[e] = ri;
+      acc += ri * ri;
+    }
+  }
+  const double v[1] = {acc};
+  if (grid_reduce<R, 1>(v, partials, counter, smem, out)) {
+    const int t = threadIdx.x;
+    if (t < R) {
+      ColState &cs = cols[t];
+      if (cs.active) {
+        cs.iters += 1;
+        cs.rr = out[t];
+        if (!isfinite(cs.rr)) { cs.status = ICPCG_E_NONFINITE; cs.active = 0; }
+        else if (cs.rr <= cs.tol2) { cs.conv = 1; cs.active = 0; }
+        else if (cs.iters >= max_iter) { cs.status = ICPCG_E_MAXITER; cs.active = 0; }
+      }
+    }
+    __syncthreads();
+    count_flags<R>(cols, flags);
+  }
+}
+
+// W holds A x on entry and b - A x on exit.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_true_residual(int64_t n, const double *__restrict__ B, double *__restrict__ W,
+                                                          double *partials, unsigned *counter, ColState *cols,
+                                                          int64_t max_iter, int max_replace, int final_pass,
+                                                          SolveFlags *flags) {
+  __shared__ double smem[kRedBlock];
+  __shared__ double out[R];
+  double acc = 0.0;
+  ICPCG_GRID_LOOP(e, n * R) {
+    const double t = B[e] - W[e];
+    W[e] = t;
+    acc += t * t;
+  }
+  const double v[1] = {acc};
+  if (grid_reduce<R, 1>(v, partials, counter, smem, out)) {
+    const int t = threadIdx.x;
+    if (t < R) {
+      ColState &cs = cols[t];
+      cs.trr = out[t];
+      if (!final_pass && cs.conv) {
+        cs.conv = 0;
+        if (cs.trr <= cs.tol2) {
+          // converged: status stays OK
+        } else if (cs.repl < max_replace) {
+          cs.repl += 1;
+          cs.rr = cs.trr;
+          if (cs.iters >= max_iter) {
+            cs.status = ICPCG_E_MAXITER;
+          } else {
+            cs.replace = 1;
+            cs.active = 1;
+          }
+        } else {
+          cs.status = ICPCG_E_TRUE_RESIDUAL;
+        }
+      }
+    }
+    __syncthreads();
+    count_flags<R>(cols, flags);
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_replace_r(int64_t n, const double *__restrict__ W, double *__restrict__ r,
+                                                      const ColState *__restrict__ cols) {
+  ICPCG_GRID_LOOP(e, n * R) {
+    if (cols[e % R].replace) r[e] = W[e];
+  }
+}
+
+__global__ void k_gather_cols(int64_t n, int R, const double *__restrict__ src, int64_t lds, int64_t c0, int nc,
+                              double *__restrict__ dst) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * R; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / R;
+    const int c = (int)(e % R);
+    dst[e] = c < nc ? src[i * lds + c0 + c] : 0.0;
+  }
+}
+
+__global__ void k_scatter_cols(int64_t n, int R, const double *__restrict__ src, double *__restrict__ dst, int64_t ldd,
+                               int64_t c0, int nc) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * R; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / R;
+    const int c = (int)(e % R);
+    if (c < nc) dst[i * ldd + c0 + c] = src[e];
+  }
+}
+
+template <typename T>
+__global__ void k_fill_pending(T *p, int64_t count) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = Pending<T>::get();
+}
+
+}  // namespace
+
+#define ICPCG_R_SWITCH(R, CALL)                                          \
+  switch (R) {                                                           \
+    case 1: { constexpr int RR = 1; CALL; } break;                       \
+    case 2: { constexpr int RR = 2; CALL; } break;                       \
+    case 4: { constexpr int RR = 4; CALL; } break;                       \
+    case 8: { constexpr int RR = 8; CALL; } break;                       \
+    case 16: { constexpr int RR = 16; CALL; } break;                     \
+    default: set_error("unsupported block width"); return ICPCG_E_INVALID; \
+  }
+
+int pcg_init(int64_t n, int R, const double *B, const double *W, double *r, double *p, void *y, void *z, bool f32,
+             double rtol, double *partials, unsigned *counter, ColState *cols, int64_t max_iter, int,
+             SolveFlags *flags, hipStream_t s) {
+  const unsigned g = vec_grid(n, R);
+  if (f32) {
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_init<RR, float>), dim3(g), dim3(kBlock), 0, s, n, B, W, r, p, (float *)y,
+                                         (float *)z, rtol, partials, counter, cols, max_iter, flags));
+  } else {
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_init<RR, double>), dim3(g), dim3(kBlock), 0, s, n, B, W, r, p,
+                                         (double *)y, (double *)z, rtol, partials, counter, cols, max_iter, flags));
+  }
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int pcg_zero_x(int64_t n, int R, double *X, const ColState *cols, hipStream_t s) {
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_zero_x<RR>, dim3(vec_grid(n, R)), dim3(kBlock), 0, s, n, X, cols));
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int pcg_dot_rz(int64_t n, int R, const double *r, const void *z, bool f32, double *partials, unsigned *counter,
+               ColState *cols, SolveFlags *flags, hipStream_t s) {
+  const unsigned g = vec_grid(n, R);
+  if (f32) {
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_dot_rz<RR, float>), dim3(g), dim3(kBlock), 0, s, n, r, (const float *)z,
+                                         partials, counter, cols, flags));
+  } else {
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_dot_rz<RR, double>), dim3(g), dim3(kBlock), 0, s, n, r,
+                                         (const double *)z, partials, counter, cols, flags));
+  }
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int pcg_update_p(int64_t n, int R, const void *z, bool f32, double *p, void *y, void *zf, const ColState *cols,
+                 hipStream_t s) {
+  const unsigned g = vec_grid(n, R);
+  if (f32) {
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, float>), dim3(g), dim3(kBlock), 0, s, n, (const float *)z, p,
+                                         (float *)y, (float *)zf, cols));
+  } else {
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, double>), dim3(g), dim3(kBlock), 0, s, n, (const double *)z,
+                                         p, (double *)y, (double *)zf, cols));
+  }
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const double *w, double *partials,
+                  unsigned *counter, ColState *cols, int64_t max_iter, SolveFlags *flags, hipStream_t s) {
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_update_xr<RR>, dim3(vec_grid(n, R)), dim3(kBlock), 0, s, n, X, r, p, w,
+                                       partials, counter, cols, max_iter, flags));
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int pcg_true_residual(int64_t n, int R, const double *B, double *W, double *partials, unsigned *counter,
+                      ColState *cols, int64_t max_iter, int max_replace, int final_pass, SolveFlags *flags,
+                      hipStream_t s) {
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_true_residual<RR>, dim3(vec_grid(n, R)), dim3(kBlock), 0, s, n, B, W,
+                                       partials, counter, cols, max_iter, max_replace, final_pass, flags));
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int pcg_replace_r(int64_t n, int R, const double *W, double *r, ColState *cols, hipStream_t s) {
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_replace_r<RR>, dim3(vec_grid(n, R)), dim3(kBlock), 0, s, n, W, r, cols));
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int gather_cols(int64_t n, int R, const double *src, int64_t lds, int64_t c0, int nc, double *dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_cols, dim3(vec_grid(n, R)), dim3(kBlock), 0, s, n, R, src, lds, c0, nc, dst);
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int scatter_cols(int64_t n, int R, const double *src, double *dst, int64_t ldd, int64_t c0, int nc, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_cols, dim3(vec_grid(n, R)), dim3(kBlock), 0, s, n, R, src, dst, ldd, c0, nc);
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int fill_pending(void *p, int64_t count, bool f32, hipStream_t s) {
+  int64_t g = (count + kBlock - 1) / kBlock;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  if (f32)
+    hipLaunchKernelGGL(k_fill_pending<float>, dim3((unsigned)g), dim3(kBlock), 0, s, (float *)p, count);
+  else
+    hipLaunchKernelGGL(k_fill_pending<double>, dim3((unsigned)g), dim3(kBlock), 0, s, (double *)p, count);
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+}  // namespace icpcg

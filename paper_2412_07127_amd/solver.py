@@ -1,0 +1,290 @@
+"""Python binding over the C ABI (include/icpcg.h) with torch tensors as device
+memory and torch's current stream as the HIP stream. Argument marshalling
+only: every numerical step runs in libicpcg.so's kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+DTYPES = {"f64": L.F64, "f32": L.F32, "bf16": L.BF16}
+
+
+class IcpcgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _block_width(X: torch.Tensor, n: int, dtype=None) -> int:
+    """Checks an n x R row-major block (or an n-vector) and returns R."""
+    if not X.is_cuda or not X.is_contiguous():
+        raise ValueError("blocks must be contiguous CUDA tensors")
+    if dtype is not None and X.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {X.dtype}")
+    if X.dim() == 1:
+        R = 1
+    elif X.dim() == 2:
+        R = X.shape[1]
+    else:
+        raise ValueError("blocks are 1-D or 2-D")
+    if X.shape[0] != n:
+        raise ValueError(f"block has {X.shape[0]} rows, expected {n}")
+    return R
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclasses.dataclass
+class CSR:
+    """Square CSR matrix on the GPU: row_ptr int64, col int32, val float64."""
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return self.row_ptr.numel() - 1
+
+    @property
+    def nnz(self) -> int:
+        return self.col.numel()
+
+    @classmethod
+    def from_numpy(cls, row_ptr, col, val, device="cuda"):
+        return cls(torch.as_tensor(np.asarray(row_ptr, np.int64)).to(device),
+                   torch.as_tensor(np.asarray(col, np.int32)).to(device),
+                   torch.as_tensor(np.asarray(val, np.float64)).to(device))
+
+    def numpy(self):
+        return (self.row_ptr.cpu().numpy(), self.col.cpu().numpy(), self.val.cpu().numpy())
+
+    def check(self):
+        for t, dt in ((self.row_ptr, torch.int64), (self.col, torch.int32), (self.val, torch.float64)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"CSR arrays must be contiguous CUDA tensors of {dt}")
+        if self.val.numel() != self.col.numel():
+            raise ValueError("val and col lengths differ")
+
+    def cstruct(self) -> L.Csr:
+        self.check()
+        return L.Csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr())
+
+
+class Context:
+    """An icpcg context bound to the current device; every call runs on
+    torch's current stream."""
+
+    def __init__(self):
+        self.lib = L.load()
+        h = C.c_void_p()
+        self._check(self.lib.icpcg_create(C.byref(h), _stream()), ctx=None)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.icpcg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, ctx="self"):
+        if st != 0:
+            msg = ""
+            if ctx == "self" and getattr(self, "h", None):
+                msg = (self.lib.icpcg_last_error(self.h) or b"").decode()
+            raise IcpcgError(st, msg or self.lib.icpcg_status_string(st).decode())
+
+    def _bind(self):
+        self.lib.icpcg_set_stream(self.h, _stream())
+
+    # ------------------------------------------------------------- factor
+    def tril_nnz(self, A: CSR) -> int:
+        self._bind()
+        out = C.c_int64()
+        a = A.cstruct()
+        self._check(self.lib.icpcg_tril_nnz(self.h, C.byref(a), C.byref(out)))
+        return out.value
+
+    def factor(self, A: CSR, max_restarts: int = -1, alpha_min: float = 0.0, raise_on_pivot=True):
+        """IC(0) of tril(A) on the GPU. Returns (L, info dict)."""
+        m = self.tril_nnz(A)
+        dev = A.val.device
+        Lr = torch.empty(A.n + 1, dtype=torch.int64, device=dev)
+        Lc = torch.empty(m, dtype=torch.int32, device=dev)
+        Lv = torch.empty(m, dtype=torch.float64, device=dev)
+        a = A.cstruct()
+        opts = L.FactorOpts(max_restarts, alpha_min)
+        info = L.FactorInfo()
+        st = self.lib.icpcg_factor(self.h, C.byref(a), _ptr(Lr), _ptr(Lc), _ptr(Lv), C.byref(opts), C.byref(info))
+        if st != 0 and (raise_on_pivot or st != L.E_PIVOT):
+            self._check(st)
+        return CSR(Lr, Lc, Lv), dict(alpha=info.alpha, restarts=info.restarts, min_pivot=info.min_pivot,
+                                     nlevels=info.nlevels, status=st)
+
+    # ---------------------------------------------------- preconditioner
+    def prec(self, Lf: CSR, dtype: str = "f64") -> "Preconditioner":
+        self._bind()
+        h = C.c_void_p()
+        l = Lf.cstruct()
+        self._check(self.lib.icpcg_prec_create(self.h, C.byref(l), DTYPES[dtype], C.byref(h)))
+        return Preconditioner(self, h, Lf, dtype)
+
+    # ------------------------------------------------------------ kernels
+    def spmv(self, A: CSR, X: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._bind()
+        R = _block_width(X, A.n, torch.float64)
+        W = torch.empty_like(X) if out is None else out
+        _block_width(W, A.n, torch.float64)
+        a = A.cstruct()
+        self._check(self.lib.icpcg_spmv(self.h, C.byref(a), _ptr(X.contiguous()), _ptr(W), R))
+        return W
+
+    def solve(self, A: CSR, P: "Preconditioner", B: torch.Tensor, X0: torch.Tensor | None = None,
+              rtol: float = 1e-8, max_iter: int = 0, max_replace: int = 3, block_width: int = 0,
+              check_every: int = 1, raise_on_error: bool = False):
+        """PCG (supplementary Algorithm 1) for the columns of B. Returns (X, infos)."""
+        self._bind()
+        R = _block_width(B, A.n, torch.float64)
+        if P.n != A.n:
+            raise ValueError("preconditioner and matrix sizes differ")
+        X = torch.zeros_like(B) if X0 is None else X0.clone().contiguous()
+        if X.shape != B.shape:
+            raise ValueError("X0 and B shapes differ")
+        opts = L.SolveOpts(rtol, max_iter, max_replace, block_width, check_every, 0)
+        infos = (L.ColInfo * R)()
+        a = A.cstruct()
+        st = self.lib.icpcg_solve(self.h, C.byref(a), P.h, _ptr(B), _ptr(X), R, C.byref(opts), infos)
+        if st in (L.E_INVALID, L.E_DEVICE, L.E_NOMEM) or (st != 0 and raise_on_error):
+            self._check(st)
+        out = [dict(iters=i.iters, replacements=i.replacements, status=i.status, relres=i.relres,
+                    true_relres=i.true_relres) for i in infos]
+        return X, out
+
+    def sync(self):
+        self._check(self.lib.icpcg_sync(self.h))
+
+
+class Preconditioner:
+    """P = L L^T with cached L^T, supernode schedules and reduced-precision copies."""
+
+    def __init__(self, ctx: Context, h, Lf: CSR, dtype: str):
+        self.ctx, self.h, self.L, self.dtype = ctx, h, Lf, dtype
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.icpcg_prec_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n(self):
+        return self.L.n
+
+    def vec_dtype(self):
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+    def info(self) -> dict:
+        self.ctx._bind()
+        i = L.PrecInfo()
+        self.ctx._check(self.ctx.lib.icpcg_prec_get_info(self.ctx.h, self.h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in L.PrecInfo._fields_}
+
+    def update_values(self, val: torch.Tensor):
+        self.ctx._bind()
+        v = val.to(torch.float64).contiguous()
+        self.ctx._check(self.ctx.lib.icpcg_prec_update_values(self.ctx.h, self.h, _ptr(v)))
+        self.L = CSR(self.L.row_ptr, self.L.col, v)
+
+    def levels(self) -> dict:
+        info = self.info()
+        dev = self.L.val.device
+        n = self.n
+        mk = lambda m: torch.empty(m, dtype=torch.int32, device=dev)
+        out = dict(level_L=mk(n), perm_L=mk(n), level_ptr_L=mk(info["nlevels_L"] + 1),
+                   level_U=mk(n), perm_U=mk(n), level_ptr_U=mk(info["nlevels_U"] + 1))
+        self.ctx._bind()
+        self.ctx._check(self.ctx.lib.icpcg_prec_levels(
+            self.ctx.h, self.h, *[_ptr(out[k]) for k in ("level_L", "perm_L", "level_ptr_L",
+                                                          "level_U", "perm_U", "level_ptr_U")]))
+        return out
+
+    def transpose(self) -> CSR:
+        dev = self.L.val.device
+        U = CSR(torch.empty(self.n + 1, dtype=torch.int64, device=dev),
+                torch.empty(self.L.nnz, dtype=torch.int32, device=dev),
+                torch.empty(self.L.nnz, dtype=torch.float64, device=dev))
+        self.ctx._bind()
+        self.ctx._check(self.ctx.lib.icpcg_prec_transpose(self.ctx.h, self.h, _ptr(U.row_ptr), _ptr(U.col),
+                                                          _ptr(U.val)))
+        return U
+
+    def _width(self, X):
+        return _block_width(X, self.n)
+
+    def trsv(self, Rhs: torch.Tensor, transpose: bool = False) -> torch.Tensor:
+        self.ctx._bind()
+        r64 = Rhs.dtype == torch.float64
+        if self.dtype == "f64" and not r64:
+            raise ValueError("an f64 preconditioner takes float64 blocks")
+        if self.dtype != "f64" and not r64 and Rhs.dtype != torch.float32:
+            raise ValueError("blocks must be float32 or float64")
+        if transpose and self.dtype != "f64" and r64:
+            raise ValueError("the backward solve of a reduced-precision preconditioner takes float32 blocks")
+        Y = torch.empty(Rhs.shape, dtype=self.vec_dtype(), device=Rhs.device)
+        Rc = Rhs.contiguous()
+        self._width(Rc)
+        self.ctx._check(self.ctx.lib.icpcg_trsv(self.ctx.h, self.h, int(transpose), _ptr(Rc), int(r64), _ptr(Y),
+                                                self._width(Rhs)))
+        return Y
+
+    def apply(self, Rhs: torch.Tensor):
+        """Y = L^-1 R, Z = L^-T Y. Returns (Y, Z)."""
+        self.ctx._bind()
+        r64 = Rhs.dtype == torch.float64
+        if self.dtype == "f64" and not r64:
+            raise ValueError("an f64 preconditioner takes float64 blocks")
+        Y = torch.empty(Rhs.shape, dtype=self.vec_dtype(), device=Rhs.device)
+        Z = torch.empty_like(Y)
+        Rc = Rhs.contiguous()
+        self._width(Rc)
+        self.ctx._check(self.ctx.lib.icpcg_apply(self.ctx.h, self.h, _ptr(Rc), int(r64), _ptr(Y), _ptr(Z),
+                                                 self._width(Rhs)))
+        return Y, Z
+
+    def apply_backward(self, G: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor):
+        """Gradients of Z = L^-T L^-1 R given G = dl/dZ. Returns (dR, dL_val)."""
+        self.ctx._bind()
+        dt = self.vec_dtype()
+        G = G.to(dt).contiguous()
+        for T in (Y, Z):
+            if T.shape != G.shape or T.dtype != dt:
+                raise ValueError("Y, Z must match G's shape and the preconditioner's block dtype")
+        Ybar = torch.empty_like(G)
+        dR = torch.empty_like(G)
+        dL = torch.empty(self.L.nnz, dtype=dt, device=G.device)
+        self.ctx._check(self.ctx.lib.icpcg_apply_backward(self.ctx.h, self.h, _ptr(G), _ptr(Y.contiguous()),
+                                                          _ptr(Z.contiguous()), _ptr(Ybar), _ptr(dR), _ptr(dL),
+                                                          self._width(G)))
+        return dR, dL

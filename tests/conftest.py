@@ -26,3 +26,12 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    # name the case on the real stderr before it runs (survives a crash that
+    # loses pytest's captured output)
+    sys.__stderr__.write(f"\n>>> {request.node.nodeid}\n")
+    sys.__stderr__.flush()
+    yield

@@ -1,0 +1,292 @@
+"""GPU kernels through the C ABI against the FP64 oracle, element by element
+(small and mid-size cases spanning many tiles and ragged tails)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2412_07127_amd as pkg
+from gpu_common import config_problem, named_matrix, oracle_factor, random_lower_pattern, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch.cuda.set_device(0)
+    return pkg.Context()
+
+
+def to_gpu(A):
+    return pkg.CSR.from_numpy(*A, device="cuda")
+
+
+def cols_of(X):
+    return X if X.ndim == 2 else X[:, None]
+
+
+# ---------------------------------------------------------------- SpMV
+
+@pytest.mark.parametrize("key", ["cfg0", "lap7", "q1e3s2.0", "tridiag"])
+@pytest.mark.parametrize("R", [1, 2, 4, 8, 16])
+def test_spmv(ctx, key, R):
+    A = named_matrix(key)
+    n = A[0].shape[0] - 1
+    X = np.random.default_rng(R).standard_normal((n, R))
+    W = ctx.spmv(to_gpu(A), torch.from_numpy(X).cuda()).cpu().numpy()
+    for c in range(R):
+        ref = oracle.spmv(*A, X[:, c])
+        assert np.abs(W[:, c] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+# -------------------------------------------------------------- levels
+
+LEVEL_CASES = ["cfg0", "q1e5s1.0", "lap7", "tridiag", "diag", "randlow", "one"]
+
+
+def level_matrix(key):
+    if key == "diag":
+        n = 1000
+        return np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32), np.full(n, 2.0)
+    if key == "randlow":
+        return random_lower_pattern(3000, 0.004, 5)
+    if key == "one":
+        return np.array([0, 1], np.int64), np.array([0], np.int32), np.array([3.0])
+    A = named_matrix(key)
+    return oracle.tril(*A)
+
+
+@pytest.mark.parametrize("key", LEVEL_CASES)
+def test_levels_bit_exact(ctx, key):
+    L = level_matrix(key)
+    P = ctx.prec(to_gpu(L), "f64")
+    g = {k: v.cpu().numpy() for k, v in P.levels().items()}
+    lev, nl = oracle.levels_lower(L[0], L[1])
+    perm, lp = oracle.level_sort(lev, nl)
+    levu, nlu = oracle.levels_upper(L[0], L[1])
+    permu, lpu = oracle.level_sort(levu, nlu)
+    assert np.array_equal(g["level_L"], lev)
+    assert np.array_equal(g["perm_L"], perm)
+    assert np.array_equal(g["level_ptr_L"], lp)
+    assert np.array_equal(g["level_U"], levu)
+    assert np.array_equal(g["perm_U"], permu)
+    assert np.array_equal(g["level_ptr_U"], lpu)
+    info = P.info()
+    assert info["nlevels_L"] == nl and info["nlevels_U"] == nlu
+    # supernodes never lengthen the dependency chain
+    assert info["nsn_levels_L"] <= nl and info["nsn_levels_U"] <= nlu
+
+
+def test_supernode_levels_q1():
+    """3-DOF nodes form supernodes: node-level count 7E - 3 for the Q1 grid."""
+    ctx = pkg.Context()
+    for E in (2, 4, 8):
+        A = named_matrix(f"q1e{E}s1.0")
+        L = oracle.tril(*A)
+        info = ctx.prec(to_gpu(L), "f64").info()
+        n = L[0].shape[0] - 1
+        assert info["nsupernodes_L"] == n // 3 and info["nsupernodes_U"] == n // 3
+        assert info["nsn_levels_L"] == 7 * E - 3
+        assert info["nsn_levels_U"] == 7 * E - 3
+
+
+@pytest.mark.parametrize("key", ["cfg0", "randlow", "tridiag"])
+def test_transpose_exact(ctx, key):
+    L = level_matrix(key)
+    P = ctx.prec(to_gpu(L), "f64")
+    U = P.transpose().numpy()
+    Ur = oracle.transpose(*L)
+    for a, b in zip(U, Ur):
+        assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- SpTRSV
+
+@pytest.mark.parametrize("key", ["cfg0", "q1e5s2.0", "lap7", "tridiag", "randlow"])
+@pytest.mark.parametrize("R", [1, 4, 16])
+def test_trsv_f64(ctx, key, R):
+    if key == "randlow":
+        L = random_lower_pattern(3000, 0.004, 5)
+    else:
+        _, L, _, _ = oracle_factor(key)
+    U = oracle.transpose(*L)
+    n = L[0].shape[0] - 1
+    P = ctx.prec(to_gpu(L), "f64")
+    Rh = np.random.default_rng(R + 1).standard_normal((n, R))
+    Y = P.trsv(torch.from_numpy(Rh).cuda()).cpu().numpy()
+    Z = P.trsv(torch.from_numpy(Y).cuda(), transpose=True).cpu().numpy()
+    for c in range(R):
+        y = oracle.trsv_lower(*L, Rh[:, c])
+        z = oracle.trsv_upper(*U, y)
+        assert relerr(Y[:, c], y) <= 1e-12
+        assert relerr(Z[:, c], z) <= 1e-12
+
+
+@pytest.mark.parametrize("dt,prec", [("f32", 1), ("bf16", 2)])
+def test_apply_reduced_precision(ctx, dt, prec):
+    A, L, U, _ = oracle_factor("cfg0")
+    n = L[0].shape[0] - 1
+    P = ctx.prec(to_gpu(L), dt)
+    r = np.random.default_rng(0).standard_normal(n)
+    _, Z = P.apply(torch.from_numpy(r).cuda())
+    z_emul = oracle.apply_f32(L, U, r, prec)   # float emulation of the same arithmetic
+    _, z64 = oracle.apply(L, U, r)
+    z = Z.double().cpu().numpy()
+    e_emul = relerr(z, z_emul)
+    e64 = relerr(z, z64)
+    print(f"{dt}: |z-z_emul|/|z|={e_emul:.2e} |z-z_f64|/|z|={e64:.2e}")
+    assert e_emul <= (1e-5 if dt == "f32" else 1e-4)
+    assert e64 <= (1e-4 if dt == "f32" else 5e-2)
+
+
+# ---------------------------------------------------------------- IC(0)
+
+@pytest.mark.parametrize("key", ["cfg0", "q1e5s2.0", "lap7", "tridiag", "kershaw", "cfg1"])
+def test_factor(ctx, key):
+    A, L, U, alpha = oracle_factor(key)
+    Lg, info = ctx.factor(to_gpu(A))
+    assert info["alpha"] == alpha
+    g = Lg.numpy()
+    assert np.array_equal(g[0], L[0]) and np.array_equal(g[1], L[1])
+    err = np.abs(g[2] - L[2]).max() / np.abs(L[2]).max()
+    assert err <= 1e-12, err
+
+
+# ------------------------------------------------------------------ PCG
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_solve_f64_matches_oracle(ctx, idx):
+    prob, b = config_problem(idx)
+    Ah = (prob.row_ptr, prob.col, prob.val)
+    A = to_gpu(Ah)
+    Lg, _ = ctx.factor(A)
+    P = ctx.prec(Lg, "f64")
+    X, info = ctx.solve(A, P, torch.from_numpy(b).cuda(), rtol=1e-8)
+    _, L, U, _ = oracle_factor(f"cfg{idx}")
+    ref = oracle.pcg(Ah, L, U, b, rtol=1e-8)
+    k = info[0]["iters"]
+    print(f"cfg{idx}: gpu iters {k} oracle iters {ref['iters']} true relres {info[0]['true_relres']:.3e}")
+    assert info[0]["status"] == pkg._lib.OK
+    assert abs(k - ref["iters"]) <= 1
+    assert info[0]["true_relres"] <= 1e-8
+    same_k = oracle.pcg(Ah, L, U, b, rtol=0.0, max_iter=k, max_replace=0)
+    assert relerr(X.cpu().numpy(), same_k["x"]) <= 1e-10
+
+
+def test_multi_rhs_columns_match_oracle(ctx):
+    prob, _ = config_problem(0)
+    Ah = (prob.row_ptr, prob.col, prob.val)
+    A = to_gpu(Ah)
+    _, L, U, _ = oracle_factor("cfg0")
+    P = ctx.prec(to_gpu(L), "f64")
+    n = prob.n
+    B = np.random.default_rng(11).standard_normal((n, 5))
+    B[:, 3] *= 1e-3
+    X, info = ctx.solve(A, P, torch.from_numpy(B).cuda(), rtol=1e-8)
+    Xh = X.cpu().numpy()
+    for c in range(5):
+        k = info[c]["iters"]
+        ref = oracle.pcg(Ah, L, U, B[:, c], rtol=1e-8)
+        assert info[c]["status"] == 0 and abs(k - ref["iters"]) <= 1
+        same_k = oracle.pcg(Ah, L, U, B[:, c], rtol=0.0, max_iter=k, max_replace=0)
+        assert relerr(Xh[:, c], same_k["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_solve_reduced_precision(ctx, dt):
+    prob, b = config_problem(1)
+    Ah = (prob.row_ptr, prob.col, prob.val)
+    A = to_gpu(Ah)
+    Lg, _ = ctx.factor(A)
+    P = ctx.prec(Lg, dt)
+    X, info = ctx.solve(A, P, torch.from_numpy(b).cuda(), rtol=1e-8)
+    _, L, U, _ = oracle_factor("cfg1")
+    ref = oracle.pcg(Ah, L, U, b, rtol=1e-8)
+    x = X.cpu().numpy()
+    tr = relerr(oracle.spmv(*Ah, x), b)
+    err = relerr(x, ref["x"])
+    print(f"{dt}: iters {info[0]['iters']} (fp64 oracle {ref['iters']}), true relres {tr:.3e}, "
+          f"|x - x_oracle|/|x_oracle| = {err:.3e}, replacements {info[0]['replacements']}")
+    assert info[0]["status"] == 0
+    assert tr <= 1e-8
+    assert err <= 1e-5
+
+
+# ------------------------------------------------------------- adjoint
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_adjoint_matches_oracle(ctx, dt):
+    _, L, U, _ = oracle_factor("q1e5s2.0")
+    n = L[0].shape[0] - 1
+    R = 8
+    rng = np.random.default_rng(3000)
+    Rh = rng.standard_normal((n, R))
+    G = rng.standard_normal((n, R))
+    ref = oracle.apply_adjoint(L, U, Rh, G)
+    P = ctx.prec(to_gpu(L), dt)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    Y, Z = P.apply(torch.from_numpy(Rh).cuda().to(tdt))
+    dR, dL = P.apply_backward(torch.from_numpy(G).cuda(), Y, Z)
+    ez = relerr(Z.double().cpu().numpy(), ref["Z"])
+    er = relerr(dR.double().cpu().numpy(), ref["Rbar"])
+    el = relerr(dL.double().cpu().numpy(), ref["dL"])
+    print(f"{dt}: Z {ez:.2e} dR {er:.2e} dL {el:.2e}")
+    tol = 1e-10 if dt == "f64" else 1e-3
+    assert ez <= tol and er <= tol and el <= tol
+
+
+# ------------------------------------------------------------ edge cases
+
+def test_zero_rhs_and_exact_start(ctx):
+    prob, b = config_problem(0)
+    A = to_gpu((prob.row_ptr, prob.col, prob.val))
+    Lg, _ = ctx.factor(A)
+    P = ctx.prec(Lg, "f64")
+    X, info = ctx.solve(A, P, torch.zeros(prob.n, dtype=torch.float64, device="cuda"),
+                        X0=torch.ones(prob.n, dtype=torch.float64, device="cuda"))
+    assert info[0]["iters"] == 0 and info[0]["status"] == 0
+    assert torch.count_nonzero(X).item() == 0
+    Bt = torch.from_numpy(b).cuda()
+    X1, info1 = ctx.solve(A, P, Bt, rtol=1e-10)
+    X2, info2 = ctx.solve(A, P, Bt, X0=X1, rtol=1e-6)
+    assert info2[0]["iters"] == 0 and torch.equal(X1, X2)
+
+
+def test_max_iter_and_nonfinite(ctx):
+    prob, b = config_problem(0)
+    A = to_gpu((prob.row_ptr, prob.col, prob.val))
+    Lg, _ = ctx.factor(A)
+    P = ctx.prec(Lg, "f64")
+    X, info = ctx.solve(A, P, torch.from_numpy(b).cuda(), rtol=1e-30, max_iter=5)
+    assert info[0]["status"] == pkg._lib.E_MAXITER and info[0]["iters"] == 5
+    bad = b.copy()
+    bad[7] = np.nan
+    X, info = ctx.solve(A, P, torch.from_numpy(bad).cuda())
+    assert info[0]["status"] == pkg._lib.E_NONFINITE
+
+
+def test_invalid_inputs_rejected(ctx):
+    rp, ci, v = named_matrix("lap7")
+    ci2 = ci.copy()
+    ci2[[3, 4]] = ci2[[4, 3]]  # unsorted row
+    with pytest.raises(pkg.IcpcgError) as e:
+        ctx.factor(to_gpu((rp, ci2, v)))
+    assert e.value.status == pkg._lib.E_INVALID
+    # a factor with an entry above the diagonal is rejected
+    L = oracle.tril(rp, ci, v)
+    Lbad = (L[0], L[1].copy(), L[2])
+    Lbad[1][L[0][5]] = 6
+    with pytest.raises(pkg.IcpcgError):
+        ctx.prec(to_gpu(Lbad), "f64")
+    # non-positive diagonal
+    Lneg = (L[0], L[1], L[2].copy())
+    Lneg[2][L[0][3] - 1] = -1.0
+    with pytest.raises(pkg.IcpcgError):
+        ctx.prec(to_gpu(Lneg), "f64")
+
+
+def test_pivot_breakdown_gives_up_with_status(ctx):
+    A = named_matrix("kershaw")
+    Lg, info = ctx.factor(to_gpu(A), max_restarts=0, raise_on_pivot=False)
+    assert info["status"] == pkg._lib.E_PIVOT and info["alpha"] == 0.0
