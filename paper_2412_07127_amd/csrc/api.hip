@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -150,6 +151,7 @@ icpcg_status icpcg_create(icpcg_ctx **out, void *stream) {
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0)
     ctx->dev.wall_hz = (long long)v * 1000LL;  // attribute is in kHz
   ctx->dev.wait_ticks = ctx->dev.wall_hz * 4;  // 4 s
+  if (const char *e = std::getenv("ICPCG_TRSV_WAVES_PER_CU")) ctx->dev.trsv_waves_per_cu = std::atoi(e);
   if (ensure_flags(ctx) != ICPCG_OK) {
     delete ctx;
     return ICPCG_E_NOMEM;
@@ -263,6 +265,16 @@ icpcg_status icpcg_prec_create(icpcg_ctx *ctx, const icpcg_csr *L, icpcg_dtype d
   hipStream_t s = ctx->stream;
   int st = check_matrix(ctx, L, 1);
   if (st) return finish(ctx, st);
+  if (L->nnz >= ((int64_t)1 << 31)) return fail(ctx, ICPCG_E_INVALID, "prec_create: factor has 2^31 or more entries");
+  {
+    DevBuf lens;
+    if (lens.reserve(L->n * 4)) return finish(ctx, ICPCG_E_NOMEM);
+    hipLaunchKernelGGL(k_row_len, dim3(1024), dim3(256), 0, s, L->row_ptr, L->n, lens.as<int32_t>());
+    int32_t maxlen = 0;
+    if ((st = reduce_max_i32(lens.as<int32_t>(), L->n, s, &maxlen))) return finish(ctx, st);
+    if (maxlen >= (1 << 27))
+      return fail(ctx, ICPCG_E_INVALID, "prec_create: a factor row has 2^27 or more entries");
+  }
   icpcg_prec *P = new (std::nothrow) icpcg_prec();
   if (!P) return finish(ctx, ICPCG_E_NOMEM);
   P->n = L->n;

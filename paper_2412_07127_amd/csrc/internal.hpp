@@ -48,6 +48,7 @@ struct DevBuf {
 struct Device {
   int id = 0;
   int num_cu = 256;
+  int trsv_waves_per_cu = 0;  // 0: as many as fit
   long long wall_hz = 100000000;  // wall_clock64 rate
   long long wait_ticks = 400000000;  // device-side wait limit (4 s)
 };
@@ -90,11 +91,21 @@ struct icpcg_ctx {
   std::vector<Tune> tunes;
 };
 
+// One schedule position of a triangular solve: the supernode's first row a,
+// the start of that row in the CSR arrays, and (m << 3) | size with m the
+// number of shared off-block entries.
+struct SnItem {
+  int64_t ro0;
+  int32_t a;
+  int32_t m_sz;
+};
+
 // One triangular factor's schedule: supernodes (row ranges solved together)
 // ordered by level.
 struct TriSchedule {
   icpcg::DevBuf sn_ptr;    // int32[nsn + 1]
   icpcg::DevBuf sn_order;  // int32[nsn]: supernodes sorted by (level, id)
+  icpcg::DevBuf items;     // SnItem[nsn] in schedule order
   int64_t nsn = 0;
   int64_t nlev = 0;
 };

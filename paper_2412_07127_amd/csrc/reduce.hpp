@@ -68,6 +68,41 @@ __device__ bool grid_reduce(const double (&v)[K], double *partials, unsigned *co
   return true;
 }
 
+// Same as grid_reduce<R, 1>, for the lane layout where a thread holds CPL
+// consecutive columns starting at ((t % (R / CPL)) * CPL).
+template <int R, int CPL>
+__device__ bool grid_reduce_cpl(const double (&v)[CPL], double *partials, unsigned *counter, double *smem,
+                                double *out) {
+  constexpr int LPR = R / CPL;
+  __shared__ unsigned ticket;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) smem[k * kRedBlock + t] = v[k];
+  __syncthreads();
+  block_fold<LPR, CPL>(smem);
+  if (t < LPR) {
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) partials[(int64_t)blockIdx.x * R + t * CPL + k] = smem[k * kRedBlock + t];
+  }
+  __threadfence();
+  __syncthreads();
+  if (t == 0) ticket = atomicAdd(counter, 1u);
+  __syncthreads();
+  if (ticket != gridDim.x - 1) return false;
+  __threadfence();
+  const int c = t % R;
+  const int nb = (int)gridDim.x;
+  double acc = 0.0;
+  for (int b = t / R; b < nb; b += kRedBlock / R) acc += partials[(int64_t)b * R + c];
+  smem[t] = acc;
+  __syncthreads();
+  block_fold<R, 1>(smem);
+  if (t < R) out[t] = smem[t];
+  if (t == 0) *counter = 0u;
+  __syncthreads();
+  return true;
+}
+
 // Refresh the host-visible counters from the column states (last block only,
 // after its finalizer has run).
 template <int R>

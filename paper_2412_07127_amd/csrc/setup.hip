@@ -218,6 +218,11 @@ __global__ __launch_bounds__(kBlock) void k_levels(const int64_t *__restrict__ r
     const int64_t row = UPPER ? b - 1 : a;
     const int64_t s = rp[row], e = rp[row + 1];
     const int64_t lo = UPPER ? s + 1 : s, hi = UPPER ? e : e - 1;
+    // one lane waits for the nearest dependency (usually the last to finish)
+    if (hi > lo && lane == 0) {
+      const int32_t j = ci[UPPER ? lo : hi - 1];
+      (void)wait_int(level + (IDENT ? j : sn_of_row[j]), err, limit);
+    }
     int mx = -1;
     for (int64_t q = lo + lane; q < hi; q += 64) {
       const int32_t j = ci[q];
@@ -227,6 +232,21 @@ __global__ __launch_bounds__(kBlock) void k_levels(const int64_t *__restrict__ r
     }
     mx = wave_max_int(mx);
     if (lane == 0) st_agent(level + item, mx + 1);
+  }
+}
+
+// Schedule records in level order (see SnItem).
+__global__ void k_sched_items(const int32_t *__restrict__ order, const int32_t *__restrict__ sn_ptr,
+                              const int64_t *__restrict__ rp, int64_t nsn, bool upper, SnItem *__restrict__ items) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nsn; t += (int64_t)gridDim.x * blockDim.x) {
+    const int s = order[t];
+    const int a = sn_ptr[s], sz = sn_ptr[s + 1] - a;
+    const int64_t m = upper ? rp[a + sz] - rp[a + sz - 1] - 1 : rp[a + 1] - rp[a] - 1;
+    SnItem it;
+    it.ro0 = rp[a];
+    it.a = a;
+    it.m_sz = (int32_t)((m << 3) | sz);
+    items[t] = it;
   }
 }
 
@@ -435,7 +455,13 @@ int build_schedule(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, 
   }
   ICPCG_HIP_TRY(hipGetLastError());
   if ((st = check_err_flag(err, s, "supernode level analysis"))) return st;
-  return sort_by_level(level.as<int32_t>(), nsn, out.sn_order.as<int32_t>(), nullptr, &out.nlev, s);
+  if ((st = sort_by_level(level.as<int32_t>(), nsn, out.sn_order.as<int32_t>(), nullptr, &out.nlev, s))) return st;
+  if (out.items.reserve((size_t)nsn * sizeof(SnItem))) return ICPCG_E_NOMEM;
+  hipLaunchKernelGGL(k_sched_items, dim3(grid_rows(nsn, kBlock)), dim3(kBlock), 0, s, out.sn_order.as<int32_t>(),
+                     out.sn_ptr.as<int32_t>(), rp, (int64_t)nsn, upper, out.items.as<SnItem>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  ICPCG_HIP_TRY(hipStreamSynchronize(s));
+  return ICPCG_OK;
 }
 
 // Row level sets (bit-exact integers): level, rows sorted by (level, row) and

@@ -12,15 +12,22 @@
 //    resident waves. A wave does not wait for a whole level, only for the
 //    x_j it reads: the output array starts filled with a reserved NaN
 //    pattern, every result is published with a device-scope store, and a
-//    reader spins on a device-scope load until the pattern is gone (the value
-//    is its own flag, so no fences are needed). The smallest unfinished
-//    position is always held by a running wave whose inputs are done, so the
-//    co-resident grid always progresses; a wall-clock limit turns an
-//    impossible wait into an error instead of a hang.
-//  * Lanes of a wave are (slot, column): SLOTS = 64 / R lanes stride over the
-//    off-block entries, R lanes cover the columns of one gathered row of the
-//    row-major block (one contiguous load). Partial sums meet in a fixed
-//    butterfly, so results are deterministic.
+//    reader checks each value with a device-scope load (the value is its own
+//    flag, so no fences are needed). The smallest unfinished position is
+//    always held by a running wave whose inputs are done, so the co-resident
+//    grid always progresses; a wall-clock limit turns an impossible wait into
+//    an error instead of a hang.
+//  * Latency: every item's metadata is one 16-byte record in schedule order,
+//    fetched one item ahead; indices, factor values, the diagonal block and
+//    the right-hand side are loaded before any wait; all dependencies are
+//    gathered in one round, and only while some are still pending does a
+//    single lane poll one of them (with a short backoff) before the pending
+//    ones are loaded again, so thousands of waiting waves do not flood the
+//    memory system and a ready input costs one round trip.
+//  * Lanes of a wave are (slot, column group): a lane owns CPL consecutive
+//    columns (CPL = min(R, 4)), R / CPL lanes cover one gathered row of the
+//    row-major block (one contiguous load) and the SLOTS slots stride over the
+//    off-block entries. Partial sums meet in a fixed butterfly (deterministic).
 //  * Factor values may be FP64, FP32 or bfloat16 (widened to FP32); FP32 and
 //    bfloat16 factors run FP32 arithmetic.
 #include "internal.hpp"
@@ -39,110 +46,242 @@ __device__ __forceinline__ T xor_sum_hi(T v) {
   return v;
 }
 
-template <typename TV, typename TA, typename TR, int R, bool UPPER>
-__global__ __launch_bounds__(kBlock) void k_trsv(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                 const TV *__restrict__ val, const int32_t *__restrict__ sn_ptr,
-                                                 const int32_t *__restrict__ sn_order, int64_t nsn,
-                                                 const TR *__restrict__ rhs, TA *out, int *err,
-                                                 long long limit) {
-  constexpr int SLOTS = 64 / R;
-  const int lane = threadIdx.x & 63, slot = lane / R, c = lane % R;
-  const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-  const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
-  for (int64_t t = w0; t < nsn; t += nw) {
-    const int s = sn_order[t];
-    const int a = sn_ptr[s];
-    const int sz = sn_ptr[s + 1] - a;
-    int64_t ro[kSmax + 1];
-#pragma unroll
-    for (int u = 0; u <= kSmax; ++u) ro[u] = u <= sz ? rp[a + u] : 0;
-    // length of the shared off-block part and where its columns are listed
-    const int m = UPPER ? (int)(ro[sz] - ro[sz - 1]) - 1 : (int)(ro[1] - ro[0]) - 1;
-    const int64_t pcol = UPPER ? ro[sz - 1] + 1 : ro[0];
-    TA acc[kSmax];
-#pragma unroll
-    for (int u = 0; u < kSmax; ++u) acc[u] = TA(0);
-    for (int q = slot; q < m; q += SLOTS) {
-      const int j = ci[pcol + q];
-      const TA xj = wait_value<TA>(out + (int64_t)j * R + c, err, limit);
-#pragma unroll
-      for (int u = 0; u < kSmax; ++u) {
-        if (u < sz) {
-          const int64_t off = UPPER ? ro[u] + (sz - u) + q : ro[u] + q;
-          acc[u] += widen<TA>(val[off]) * xj;
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kSmax; ++u) acc[u] = xor_sum_hi<Log2<R>::v>(acc[u]);
-    if (slot == 0) {
-      TA xs[kSmax];
-      if (!UPPER) {
-#pragma unroll
-        for (int u = 0; u < kSmax; ++u) {
-          if (u < sz) {
-            const int64_t db = ro[u] + m;  // diagonal block of row a+u: columns a .. a+u
-            TA sum = (TA)rhs[(int64_t)(a + u) * R + c] - acc[u];
-#pragma unroll
-            for (int w = 0; w < kSmax; ++w)
-              if (w < u) sum -= widen<TA>(val[db + w]) * xs[w];
-            xs[u] = sum / widen<TA>(val[db + u]);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int uu = kSmax - 1; uu >= 0; --uu) {
-          if (uu < sz) {
-            // row a+uu: diagonal first, then columns a+uu+1 .. a+sz-1
-            TA sum = (TA)rhs[(int64_t)(a + uu) * R + c] - acc[uu];
-#pragma unroll
-            for (int w = 0; w < kSmax; ++w)
-              if (w > uu && w < sz) sum -= widen<TA>(val[ro[uu] + (w - uu)]) * xs[w];
-            xs[uu] = sum / widen<TA>(val[ro[uu]]);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kSmax; ++u)
-        if (u < sz) publish_value<TA>(out + (int64_t)(a + u) * R + c, xs[u]);
+// Row start of row a+u of a supernode from the first row's start: lower rows
+// grow by one diagonal-block entry per row, upper rows shrink by one.
+template <bool UPPER>
+__device__ __forceinline__ int64_t row_start(int64_t ro0, int u, int m, int sz) {
+  return UPPER ? ro0 + (int64_t)u * (sz + m) - (int64_t)u * (u - 1) / 2
+               : ro0 + (int64_t)u * (m + 1) + (int64_t)u * (u - 1) / 2;
+}
+
+// Single-lane wait until *p no longer holds the pending pattern, with a short
+// backoff. Returns false when the wall-clock limit was hit.
+template <typename U>
+__device__ __forceinline__ bool poll_one(const U *up, U pending, int *err, long long limit) {
+  if (ld_agent(up) != pending) return true;
+  const long long t0 = wall_clock64();
+  int backoff = 1;
+  for (;;) {
+    for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(1);
+    if (ld_agent(up) != pending) return true;
+    if (backoff < 4) backoff <<= 1;
+    if (wall_clock64() - t0 > limit) {
+      __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
     }
   }
 }
 
+template <typename TV, typename TA, typename TR, int R, bool UPPER, int QD>
+__global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci, const TV *__restrict__ val,
+                                                 const SnItem *__restrict__ sched, int64_t nsn,
+                                                 const TR *__restrict__ rhs, TA *out, int *err, long long limit) {
+  using U = typename Flag<TA>::U;
+  constexpr U kPend = Flag<TA>::kPending;
+  constexpr int CPL = R >= 4 ? 4 : R;   // columns per lane
+  constexpr int LPR = R / CPL;          // lanes per gathered row
+  constexpr int SLOTS = 64 / LPR;       // entry slots per wave
+  constexpr int NDB = kSmax * (kSmax + 1) / 2;  // stored entries of a dense diagonal block
+  const int lane = threadIdx.x & 63, slot = lane / LPR, c0 = (lane % LPR) * CPL;
+  const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
+  const U *outb = reinterpret_cast<const U *>(out);
+  SnItem nxt;
+  if (w0 < nsn) nxt = sched[w0];
+  for (int64_t t = w0; t < nsn; t += nw) {
+    const SnItem it = nxt;
+    if (t + nw < nsn) nxt = sched[t + nw];  // next item's record arrives while this one runs
+    const int a = it.a, sz = it.m_sz & 7, m = it.m_sz >> 3;
+    int64_t ro[kSmax];
+#pragma unroll
+    for (int u = 0; u < kSmax; ++u) ro[u] = row_start<UPPER>(it.ro0, u, m, sz);
+    // off-block columns as listed in the first row: after its sz diagonal-block
+    // entries (upper) or before its diagonal (lower)
+    const int64_t pcol = UPPER ? ro[0] + sz : ro[0];
+    // everything that does not depend on other waves is loaded first
+    int jj[QD];
+    TA vv[QD][kSmax];
+#pragma unroll
+    for (int k = 0; k < QD; ++k) {
+      const int q = slot + k * SLOTS;
+      jj[k] = q < m ? ci[pcol + q] : 0;
+#pragma unroll
+      for (int u = 0; u < kSmax; ++u)
+        vv[k][u] = (q < m && u < sz) ? widen<TA>(val[UPPER ? ro[u] + (sz - u) + q : ro[u] + q]) : TA(0);
+    }
+    TA dv[NDB];   // diagonal block, row by row (lower: columns a..a+u; upper: a+u..a+sz-1)
+    TA bv[kSmax][CPL];
+    if (slot == 0) {
+#pragma unroll
+      for (int u = 0; u < kSmax; ++u) {
+#pragma unroll
+        for (int w = 0; w < kSmax; ++w) {
+          const int d = u * (u + 1) / 2 + w;  // storage index of (u, w) for w <= u in the lower order
+          if (!UPPER && w <= u) dv[d] = u < sz ? widen<TA>(val[ro[u] + m + w]) : TA(1);
+        }
+        if (UPPER) {
+          // row a+u holds columns a+u .. a+sz-1 first: store (u, u+w') at u*kSmax - u*(u-1)/2 + w'
+#pragma unroll
+          for (int w = 0; w < kSmax; ++w) {
+            const int d = u * kSmax - u * (u - 1) / 2 + w;
+            if (w < kSmax - u) dv[d] = (u < sz && w < sz - u) ? widen<TA>(val[ro[u] + w]) : TA(1);
+          }
+        }
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) bv[u][cc] = u < sz ? (TA)rhs[(int64_t)(a + u) * R + c0 + cc] : TA(0);
+      }
+    }
+    // gather the dependencies: one attempt for all, then while any is still
+    // pending one lane polls it and the pending ones are loaded again
+    U xb[QD][CPL];
+#pragma unroll
+    for (int k = 0; k < QD; ++k) {
+      const int q = slot + k * SLOTS;
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) xb[k][cc] = q < m ? ld_agent(outb + (int64_t)jj[k] * R + c0 + cc) : (U)0;
+    }
+    for (;;) {
+      bool pend = false;
+      int64_t paddr = 0;
+#pragma unroll
+      for (int k = QD - 1; k >= 0; --k)
+#pragma unroll
+        for (int cc = CPL - 1; cc >= 0; --cc)
+          if (xb[k][cc] == kPend) { pend = true; paddr = (int64_t)jj[k] * R + c0 + cc; }
+      const unsigned long long mask = __ballot(pend);
+      if (!mask) break;
+      const int leader = 63 - __clzll(mask);  // the highest pending lane: the nearest rows sit last
+      bool ok = true;
+      if (lane == leader) ok = poll_one<U>(outb + paddr, kPend, err, limit);
+      if (__ballot(!ok)) {
+#pragma unroll
+        for (int k = 0; k < QD; ++k)
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc)
+            if (xb[k][cc] == kPend) xb[k][cc] = Flag<TA>::kCanonNaN;
+        break;
+      }
+#pragma unroll
+      for (int k = 0; k < QD; ++k)
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc)
+          if (xb[k][cc] == kPend) xb[k][cc] = ld_agent(outb + (int64_t)jj[k] * R + c0 + cc);
+    }
+    TA acc[kSmax][CPL];
+#pragma unroll
+    for (int u = 0; u < kSmax; ++u)
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) acc[u][cc] = TA(0);
+#pragma unroll
+    for (int k = 0; k < QD; ++k) {
+      const int q = slot + k * SLOTS;
+      if (q < m) {
+#pragma unroll
+        for (int u = 0; u < kSmax; ++u)
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc) acc[u][cc] += vv[k][u] * bitcast<TA>(xb[k][cc]);
+      }
+    }
+    // rows longer than the prefetch window
+    for (int q = slot + QD * SLOTS; q < m; q += SLOTS) {
+      const int j = ci[pcol + q];
+      TA xv[CPL];
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) xv[cc] = wait_value<TA>(out + (int64_t)j * R + c0 + cc, err, limit);
+#pragma unroll
+      for (int u = 0; u < kSmax; ++u) {
+        if (u < sz) {
+          const TA v = widen<TA>(val[UPPER ? ro[u] + (sz - u) + q : ro[u] + q]);
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc) acc[u][cc] += v * xv[cc];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSmax; ++u)
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) acc[u][cc] = xor_sum_hi<Log2<LPR>::v>(acc[u][cc]);
+    if (slot == 0) {
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        const int c = c0 + cc;
+        TA xs[kSmax];
+        if (!UPPER) {
+#pragma unroll
+          for (int u = 0; u < kSmax; ++u) {
+            if (u < sz) {
+              TA sum = bv[u][cc] - acc[u][cc];
+#pragma unroll
+              for (int w = 0; w < kSmax; ++w)
+                if (w < u) sum -= dv[u * (u + 1) / 2 + w] * xs[w];
+              xs[u] = sum / dv[u * (u + 1) / 2 + u];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int uu = kSmax - 1; uu >= 0; --uu) {
+            if (uu < sz) {
+              const int base = uu * kSmax - uu * (uu - 1) / 2;  // (uu, uu) in the upper storage
+              TA sum = bv[uu][cc] - acc[uu][cc];
+#pragma unroll
+              for (int w = 0; w < kSmax; ++w)
+                if (w > uu && w < sz) sum -= dv[base + (w - uu)] * xs[w];
+              xs[uu] = sum / dv[base];
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kSmax; ++u)
+          if (u < sz) publish_value<TA>(out + (int64_t)(a + u) * R + c, xs[u]);
+      }
+    }
+  }
+}
+
+// Waves the solve keeps resident: all that fit (the static round-robin needs
+// the whole grid resident), or fewer when ICPCG_TRSV_WAVES_PER_CU asks.
 template <typename K>
-int resident_blocks(K kernel, const Device &dev) {
+int64_t resident_blocks(K kernel, const Device &dev) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) {
     (void)hipGetLastError();
     per_cu = 1;
   }
-  return per_cu * dev.num_cu;
+  if (dev.trsv_waves_per_cu > 0) {
+    const int want = (dev.trsv_waves_per_cu + 3) / 4;
+    if (want < per_cu) per_cu = want;
+  }
+  return (int64_t)per_cu * dev.num_cu;
 }
 
+template <int R> struct Depth { static constexpr int v = 2; };  // 64 slots: rows up to 128 prefetched
+template <> struct Depth<8> { static constexpr int v = 4; };    // 32 slots
+template <> struct Depth<16> { static constexpr int v = 4; };   // 16 slots
+
 template <typename TV, typename TA, typename TR, int R, bool UPPER>
-int launch(const TriSchedule &S, const int64_t *rp, const int32_t *ci, const TV *val, const TR *rhs, TA *out,
-           hipStream_t s, const Device &dev, int *err) {
+int launch(const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs, TA *out, hipStream_t s,
+           const Device &dev, int *err) {
   if (S.nsn == 0) return ICPCG_OK;
-  auto k = k_trsv<TV, TA, TR, R, UPPER>;
+  auto k = k_trsv<TV, TA, TR, R, UPPER, Depth<R>::v>;
   int64_t grid = resident_blocks(k, dev);
   const int64_t need = (S.nsn + 3) / 4;
   if (need < grid) grid = need;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kBlock), 0, s, rp, ci, val, S.sn_ptr.as<int32_t>(),
-                     S.sn_order.as<int32_t>(), S.nsn, rhs, out, err, dev.wait_ticks);
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kBlock), 0, s, ci, val, S.items.as<SnItem>(), S.nsn, rhs, out,
+                     err, dev.wait_ticks);
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
 }
 
 template <typename TV, typename TA, typename TR, bool UPPER>
-int dispatch_r(int R, const TriSchedule &S, const int64_t *rp, const int32_t *ci, const TV *val, const TR *rhs,
-               TA *out, hipStream_t s, const Device &dev, int *err) {
+int dispatch_r(int R, const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs, TA *out, hipStream_t s,
+               const Device &dev, int *err) {
   switch (R) {
-    case 1: return launch<TV, TA, TR, 1, UPPER>(S, rp, ci, val, rhs, out, s, dev, err);
-    case 2: return launch<TV, TA, TR, 2, UPPER>(S, rp, ci, val, rhs, out, s, dev, err);
-    case 4: return launch<TV, TA, TR, 4, UPPER>(S, rp, ci, val, rhs, out, s, dev, err);
-    case 8: return launch<TV, TA, TR, 8, UPPER>(S, rp, ci, val, rhs, out, s, dev, err);
-    case 16: return launch<TV, TA, TR, 16, UPPER>(S, rp, ci, val, rhs, out, s, dev, err);
+    case 1: return launch<TV, TA, TR, 1, UPPER>(S, ci, val, rhs, out, s, dev, err);
+    case 2: return launch<TV, TA, TR, 2, UPPER>(S, ci, val, rhs, out, s, dev, err);
+    case 4: return launch<TV, TA, TR, 4, UPPER>(S, ci, val, rhs, out, s, dev, err);
+    case 8: return launch<TV, TA, TR, 8, UPPER>(S, ci, val, rhs, out, s, dev, err);
+    case 16: return launch<TV, TA, TR, 16, UPPER>(S, ci, val, rhs, out, s, dev, err);
     default:
       set_error("trsv: unsupported block width " + std::to_string(R));
       return ICPCG_E_INVALID;
@@ -154,39 +293,36 @@ int dispatch_r(int R, const TriSchedule &S, const int64_t *rp, const int32_t *ci
 // `out` must hold the pending pattern in every entry on entry.
 int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *out, int R, int64_t, hipStream_t s,
          const Device &dev, int *err) {
-  const int64_t *rp = upper ? P->urp.as<int64_t>() : P->lrp.as<int64_t>();
   const int32_t *ci = upper ? P->uci.as<int32_t>() : P->lci.as<int32_t>();
   const TriSchedule &S = upper ? P->su : P->sl;
   if (P->dtype == ICPCG_F64) {
     const double *v = upper ? P->uval.as<double>() : P->lval.as<double>();
     if (upper)
-      return dispatch_r<double, double, double, true>(R, S, rp, ci, v, (const double *)rhs, (double *)out, s, dev, err);
-    return dispatch_r<double, double, double, false>(R, S, rp, ci, v, (const double *)rhs, (double *)out, s, dev, err);
+      return dispatch_r<double, double, double, true>(R, S, ci, v, (const double *)rhs, (double *)out, s, dev, err);
+    return dispatch_r<double, double, double, false>(R, S, ci, v, (const double *)rhs, (double *)out, s, dev, err);
   }
   if (P->dtype == ICPCG_F32) {
     const float *v = upper ? P->uval_lo.as<float>() : P->lval_lo.as<float>();
     if (upper) {
       if (rhs_f64)
-        return dispatch_r<float, float, double, true>(R, S, rp, ci, v, (const double *)rhs, (float *)out, s, dev, err);
-      return dispatch_r<float, float, float, true>(R, S, rp, ci, v, (const float *)rhs, (float *)out, s, dev, err);
+        return dispatch_r<float, float, double, true>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev, err);
+      return dispatch_r<float, float, float, true>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err);
     }
     if (rhs_f64)
-      return dispatch_r<float, float, double, false>(R, S, rp, ci, v, (const double *)rhs, (float *)out, s, dev, err);
-    return dispatch_r<float, float, float, false>(R, S, rp, ci, v, (const float *)rhs, (float *)out, s, dev, err);
+      return dispatch_r<float, float, double, false>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev, err);
+    return dispatch_r<float, float, float, false>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err);
   }
   const unsigned short *v = upper ? P->uval_lo.as<unsigned short>() : P->lval_lo.as<unsigned short>();
   if (upper) {
     if (rhs_f64)
-      return dispatch_r<unsigned short, float, double, true>(R, S, rp, ci, v, (const double *)rhs, (float *)out, s,
-                                                             dev, err);
-    return dispatch_r<unsigned short, float, float, true>(R, S, rp, ci, v, (const float *)rhs, (float *)out, s, dev,
-                                                          err);
+      return dispatch_r<unsigned short, float, double, true>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev,
+                                                             err);
+    return dispatch_r<unsigned short, float, float, true>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err);
   }
   if (rhs_f64)
-    return dispatch_r<unsigned short, float, double, false>(R, S, rp, ci, v, (const double *)rhs, (float *)out, s,
-                                                            dev, err);
-  return dispatch_r<unsigned short, float, float, false>(R, S, rp, ci, v, (const float *)rhs, (float *)out, s, dev,
-                                                         err);
+    return dispatch_r<unsigned short, float, double, false>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev,
+                                                            err);
+  return dispatch_r<unsigned short, float, float, false>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err);
 }
 
 }  // namespace icpcg
