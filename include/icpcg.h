@@ -73,6 +73,7 @@ typedef struct {
 } icpcg_csr;
 
 typedef struct icpcg_ctx icpcg_ctx;    /* stream, workspace, device properties */
+typedef struct icpcg_mat icpcg_mat;    /* A with its row-group analysis */
 typedef struct icpcg_prec icpcg_prec;  /* L, L^T, schedules, reduced-precision copies */
 
 /* ---------------------------------------------------------------- context */
@@ -195,6 +196,21 @@ icpcg_status icpcg_apply_backward(icpcg_ctx *ctx, const icpcg_prec *P, const voi
                                   const void *Y, const void *Z, void *Ybar, void *dR,
                                   void *dL_val, int64_t nrhs);
 
+/* ------------------------------------------------------ analyzed matrix */
+
+/* Analyze A once for repeated products: consecutive rows with identical
+ * column lists (the rows of one multi-DOF node) form groups of up to 3 that
+ * the SpMV reads as a unit (each column index and each gathered x row once
+ * per group). The handle keeps A's pointers: A's buffers must stay valid and
+ * unchanged while it is used. Errors: ICPCG_E_INVALID (malformed A). */
+icpcg_status icpcg_mat_create(icpcg_ctx *ctx, const icpcg_csr *A, icpcg_mat **M);
+icpcg_status icpcg_mat_destroy(icpcg_mat *M);
+
+/* W = A X through the row-group kernel (same result as icpcg_spmv up to the
+ * order of the additions inside a row). */
+icpcg_status icpcg_mat_spmv(icpcg_ctx *ctx, const icpcg_mat *M, const double *X, double *W,
+                            int64_t nrhs);
+
 /* ----------------------------------------------------------------- PCG */
 
 typedef struct {
@@ -202,7 +218,8 @@ typedef struct {
   int64_t max_iter;      /* products A p per column; <= 0: min(n, max(10, 10 sqrt n)) */
   int max_replace;       /* true-residual replacements per column (default 3 when < 0) */
   int block_width;       /* columns per pass: 0 = autotune, else 1, 2, 4, 8 or 16 */
-  int check_every;       /* host polls the convergence flags every k steps (<= 0: 1) */
+  int check_every;       /* host polls the convergence flags every k steps (<= 0: 8); steps
+                            queued after every column stopped return at once */
   int use_graph;         /* 1: replay the captured step as a hipGraph */
 } icpcg_solve_opts;
 
@@ -222,10 +239,16 @@ typedef struct {
  * is above the tolerance, r is replaced by it and the iteration continues
  * (at most max_replace times). Iterations count the products A p; b = 0
  * gives x = 0 after 0 iterations. info (nullable) receives nrhs entries.
- * Returns the worst column status. opts may be NULL (rtol 1e-8). */
+ * Returns the worst column status. opts may be NULL (rtol 1e-8). A is
+ * analyzed on each call (see icpcg_mat_create). */
 icpcg_status icpcg_solve(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P,
                          const double *B, double *X, int64_t nrhs, const icpcg_solve_opts *opts,
                          icpcg_col_info *info);
+
+/* icpcg_solve on an analyzed matrix (skips the per-call analysis). */
+icpcg_status icpcg_solve_mat(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec *P,
+                             const double *B, double *X, int64_t nrhs,
+                             const icpcg_solve_opts *opts, icpcg_col_info *info);
 
 /* Synchronize the context's stream and report a device-side failure of the
  * non-synchronizing calls (a dependency wait that hit its time limit). */

@@ -86,6 +86,10 @@ def load():
         "icpcg_apply_backward": ([P, P, P, P, P, P, P, P, i64], st),
         "icpcg_solve": ([P, C.POINTER(Csr), P, P, P, i64, C.POINTER(SolveOpts), C.POINTER(ColInfo)], st),
         "icpcg_sync": ([P], st),
+        "icpcg_mat_create": ([P, C.POINTER(Csr), C.POINTER(P)], st),
+        "icpcg_mat_destroy": ([P], st),
+        "icpcg_mat_spmv": ([P, P, P, P, i64], st),
+        "icpcg_solve_mat": ([P, P, P, P, P, i64, C.POINTER(SolveOpts), C.POINTER(ColInfo)], st),
         "icpcg_version": ([], C.c_char_p),
     }
     for name, (args, res) in sig.items():

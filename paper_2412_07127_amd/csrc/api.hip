@@ -86,9 +86,6 @@ int ensure_flags(icpcg_ctx *ctx) {
 }
 
 SolveFlags *dev_flags(icpcg_ctx *ctx) { return ctx->ws.flags.as<SolveFlags>(); }
-unsigned *dev_counter(icpcg_ctx *ctx) {
-  return reinterpret_cast<unsigned *>(ctx->ws.flags.as<char>() + sizeof(SolveFlags));
-}
 
 int read_flags(icpcg_ctx *ctx, SolveFlags *h) {
   ICPCG_HIP_TRY(hipMemcpyAsync(ctx->ws.host_flags, ctx->ws.flags.p, sizeof(SolveFlags), hipMemcpyDeviceToHost,
@@ -373,7 +370,7 @@ icpcg_status icpcg_spmv(icpcg_ctx *ctx, const icpcg_csr *A, const double *X, dou
   if (!ctx || !valid_csr_args(A) || !pow2_width(nrhs) || (A->n > 0 && (!X || !W)))
     return fail(ctx, ICPCG_E_INVALID, "spmv: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
   return finish(ctx, spmv(A->row_ptr, A->col, A->val, A->n, X, W, (int)nrhs, spmv_default_slots((int)nrhs),
-                          ctx->stream, nullptr, nullptr, nullptr, 0, 0));
+                          ctx->stream));
 }
 
 icpcg_status icpcg_trsv(icpcg_ctx *ctx, const icpcg_prec *P, int transpose, const void *R, int r_is_f64, void *Y,
@@ -431,7 +428,19 @@ struct PassBuffers {
   void *y, *z;
   double *partials;
   ColState *cols;
+  const int32_t *gptr;  // row groups of A (identical column lists)
+  int64_t ngroups;
 };
+
+// w = A x (optionally with the fused p^T w reduction) through the row-group
+// kernel when groups are available.
+int spmv_pass(const icpcg_csr *A, const PassBuffers &b, const double *x, double *y, int R, hipStream_t s,
+              double *partials = nullptr, ColState *cols = nullptr, const int *active = nullptr) {
+  if (b.gptr)
+    return spmv_grouped(A->row_ptr, A->col, A->val, b.ngroups, b.gptr, x, y, R, spmv_grouped_default_slots(R), s,
+                        partials, cols, active);
+  return spmv(A->row_ptr, A->col, A->val, A->n, x, y, R, spmv_default_slots(R), s, partials, cols, active);
+}
 
 // One block of R columns through supplementary Algorithm 1 with the stop,
 // replacement and failure rules stated in icpcg.h.
@@ -440,19 +449,14 @@ int run_pass(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const Pass
   hipStream_t s = ctx->stream;
   const int64_t n = A->n;
   const bool lo = P->dtype != ICPCG_F64;
-  const int slots = spmv_default_slots(R);
   SolveFlags *fl = dev_flags(ctx);
-  unsigned *ctr = dev_counter(ctx);
   int *err = &fl->err;
   int st;
   ICPCG_HIP_TRY(hipMemsetAsync(fl, 0, sizeof(SolveFlags), s));
-  ICPCG_HIP_TRY(hipMemsetAsync(ctr, 0, sizeof(unsigned), s));
-  if ((st = spmv(A->row_ptr, A->col, A->val, n, b.X, b.w, R, slots, s, nullptr, nullptr, nullptr, 0, 0))) return st;
-  if ((st = pcg_init(n, R, b.B, b.w, b.r, b.p, b.y, b.z, lo, o.rtol, b.partials, ctr, b.cols, max_iter, o.max_replace,
-                     fl, s)))
-    return st;
+  if ((st = spmv_pass(A, b, b.X, b.w, R, s))) return st;
+  if ((st = pcg_init(n, R, b.B, b.w, b.r, b.p, b.y, b.z, lo, o.rtol, b.partials, b.cols, max_iter, fl, s))) return st;
   if ((st = pcg_zero_x(n, R, b.X, b.cols, s))) return st;
-  const int every = o.check_every > 0 ? o.check_every : 1;
+  const int every = o.check_every > 0 ? o.check_every : 8;
   const int64_t guard = max_iter * (int64_t)(o.max_replace + 1) + 16;
   int64_t steps = 0;
   for (;;) {
@@ -464,9 +468,8 @@ int run_pass(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const Pass
     }
     if (h.n_active == 0) {
       if (h.n_conv == 0) break;
-      if ((st = spmv(A->row_ptr, A->col, A->val, n, b.X, b.w, R, slots, s, nullptr, nullptr, nullptr, 0, 0))) return st;
-      if ((st = pcg_true_residual(n, R, b.B, b.w, b.partials, ctr, b.cols, max_iter, o.max_replace, 0, fl, s)))
-        return st;
+      if ((st = spmv_pass(A, b, b.X, b.w, R, s))) return st;
+      if ((st = pcg_true_residual(n, R, b.B, b.w, b.partials, b.cols, max_iter, o.max_replace, 0, fl, s))) return st;
       if ((st = pcg_replace_r(n, R, b.w, b.r, b.cols, s))) return st;
       continue;
     }
@@ -475,28 +478,29 @@ int run_pass(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const Pass
       return ICPCG_E_DEVICE;
     }
     for (int k = 0; k < every; ++k, ++steps) {
-      if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err))) return st;
-      if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err))) return st;
-      if ((st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, ctr, b.cols, fl, s))) return st;
-      if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.z, b.cols, s))) return st;
-      if ((st = spmv(A->row_ptr, A->col, A->val, n, b.p, b.w, R, slots, s, b.partials, ctr, b.cols, max_iter, 1)))
-        return st;
-      if ((st = pcg_update_xr(n, R, b.X, b.r, b.p, b.w, b.partials, ctr, b.cols, max_iter, fl, s))) return st;
+      const int *act = &fl->n_active;
+      if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err, act))) return st;
+      if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err, act))) return st;
+      if ((st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, b.cols, fl, s))) return st;
+      if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.z, b.cols, fl, s))) return st;
+      if ((st = spmv_pass(A, b, b.p, b.w, R, s, b.partials, b.cols, act))) return st;
+      if ((st = pcg_update_xr(n, R, b.X, b.r, b.p, b.w, b.partials, b.cols, max_iter, fl, s))) return st;
     }
   }
   // final true residual of every column (reported)
-  if ((st = spmv(A->row_ptr, A->col, A->val, n, b.X, b.w, R, slots, s, nullptr, nullptr, nullptr, 0, 0))) return st;
-  if ((st = pcg_true_residual(n, R, b.B, b.w, b.partials, ctr, b.cols, max_iter, o.max_replace, 1, fl, s))) return st;
+  if ((st = spmv_pass(A, b, b.X, b.w, R, s))) return st;
+  if ((st = pcg_true_residual(n, R, b.B, b.w, b.partials, b.cols, max_iter, o.max_replace, 1, fl, s))) return st;
   return ICPCG_OK;
 }
 
 }  // namespace
 
-extern "C" icpcg_status icpcg_solve(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const double *B,
-                                    double *X, int64_t nrhs, const icpcg_solve_opts *opts, icpcg_col_info *info) {
-  if (!ctx || !valid_csr_args(A) || !P || nrhs < 1 || A->n != P->n || (A->n > 0 && (!B || !X)))
+static icpcg_status solve_impl(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec *P, const double *B, double *X,
+                               int64_t nrhs, const icpcg_solve_opts *opts, icpcg_col_info *info) {
+  const icpcg_csr *A = &M->A;
+  if (!valid_csr_args(A) || !P || nrhs < 1 || A->n != P->n || (A->n > 0 && (!B || !X)))
     return fail(ctx, ICPCG_E_INVALID, "solve: bad arguments");
-  icpcg_solve_opts o{1e-8, 0, 3, 0, 1, 0};
+  icpcg_solve_opts o{1e-8, 0, 3, 0, 8, 0};
   if (opts) o = *opts;
   if (!(o.rtol >= 0.0)) return fail(ctx, ICPCG_E_INVALID, "solve: rtol must be >= 0");
   if (o.max_replace < 0) o.max_replace = 3;
@@ -534,6 +538,8 @@ extern "C" icpcg_status icpcg_solve(icpcg_ctx *ctx, const icpcg_csr *A, const ic
     b.z = ws.z.p;
     b.partials = ws.partials.as<double>();
     b.cols = ws.cols.as<ColState>();
+    b.gptr = M->grouped ? M->gptr.as<int32_t>() : nullptr;
+    b.ngroups = M->ngroups;
     int st;
     if (gathered) {
       b.B = ws.tmp0.as<double>();
@@ -567,4 +573,61 @@ extern "C" icpcg_status icpcg_solve(icpcg_ctx *ctx, const icpcg_csr *A, const ic
     return finish(ctx, worst);
   }
   return ICPCG_OK;
+}
+
+namespace {
+int mat_init(icpcg_ctx *ctx, const icpcg_csr *A, icpcg_mat *M) {
+  M->A = *A;
+  if (A->n == 0) return ICPCG_OK;
+  int st = check_matrix(ctx, A, 0);
+  if (st) return st;
+  if ((st = build_row_groups(A->row_ptr, A->col, A->n, kSupernodeMax, M->gptr, &M->ngroups, ctx->stream))) return st;
+  M->grouped = M->ngroups < A->n && !std::getenv("ICPCG_NO_ROW_GROUPS");
+  return ICPCG_OK;
+}
+}  // namespace
+
+extern "C" icpcg_status icpcg_mat_create(icpcg_ctx *ctx, const icpcg_csr *A, icpcg_mat **out) {
+  if (!ctx || !valid_csr_args(A) || !out) return fail(ctx, ICPCG_E_INVALID, "mat_create: bad arguments");
+  *out = nullptr;
+  icpcg_mat *M = new (std::nothrow) icpcg_mat();
+  if (!M) return finish(ctx, ICPCG_E_NOMEM);
+  const int st = mat_init(ctx, A, M);
+  if (st) {
+    delete M;
+    return finish(ctx, st);
+  }
+  *out = M;
+  return ICPCG_OK;
+}
+
+extern "C" icpcg_status icpcg_mat_destroy(icpcg_mat *M) {
+  delete M;
+  return ICPCG_OK;
+}
+
+extern "C" icpcg_status icpcg_mat_spmv(icpcg_ctx *ctx, const icpcg_mat *M, const double *X, double *W, int64_t nrhs) {
+  if (!ctx || !M || !pow2_width(nrhs) || (M->A.n > 0 && (!X || !W)))
+    return fail(ctx, ICPCG_E_INVALID, "mat_spmv: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
+  const icpcg_csr *A = &M->A;
+  if (!M->grouped)
+    return finish(ctx, spmv(A->row_ptr, A->col, A->val, A->n, X, W, (int)nrhs, spmv_default_slots((int)nrhs),
+                            ctx->stream));
+  return finish(ctx, spmv_grouped(A->row_ptr, A->col, A->val, M->ngroups, M->gptr.as<int32_t>(), X, W, (int)nrhs,
+                                  spmv_grouped_default_slots((int)nrhs), ctx->stream));
+}
+
+extern "C" icpcg_status icpcg_solve_mat(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec *P, const double *B,
+                                        double *X, int64_t nrhs, const icpcg_solve_opts *opts, icpcg_col_info *info) {
+  if (!ctx || !M) return fail(ctx, ICPCG_E_INVALID, "solve: bad arguments");
+  return solve_impl(ctx, M, P, B, X, nrhs, opts, info);
+}
+
+extern "C" icpcg_status icpcg_solve(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const double *B,
+                                    double *X, int64_t nrhs, const icpcg_solve_opts *opts, icpcg_col_info *info) {
+  if (!ctx || !valid_csr_args(A)) return fail(ctx, ICPCG_E_INVALID, "solve: bad arguments");
+  icpcg_mat M;
+  const int st = mat_init(ctx, A, &M);
+  if (st) return finish(ctx, st);
+  return solve_impl(ctx, &M, P, B, X, nrhs, opts, info);
 }

@@ -15,7 +15,7 @@ namespace icpcg {
 
 // Largest supernode (rows solved together by one wave) of the triangular
 // solve schedules.
-constexpr int kSupernodeMax = 4;
+constexpr int kSupernodeMax = 3;
 
 // Last error text of the calling thread; the ABI layer copies it into the
 // context that made the call.
@@ -75,7 +75,7 @@ struct SolveFlags {
 
 // Work buffers of a context (grow monotonically).
 struct Workspace {
-  DevBuf r, p, w, y, z, partials, cols, flags, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5;
+  DevBuf r, p, w, y, z, partials, cols, flags, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, agrp;
   void *host_flags = nullptr;  // pinned SolveFlags
 };
 
@@ -108,6 +108,13 @@ struct TriSchedule {
   icpcg::DevBuf items;     // SnItem[nsn] in schedule order
   int64_t nsn = 0;
   int64_t nlev = 0;
+};
+
+struct icpcg_mat {
+  icpcg_csr A;
+  icpcg::DevBuf gptr;   // int32[ngroups + 1] row groups
+  int64_t ngroups = 0;
+  bool grouped = false;
 };
 
 struct icpcg_prec {
@@ -149,6 +156,8 @@ int build_transpose(icpcg_prec *P, hipStream_t s);
 int refresh_values(icpcg_prec *P, hipStream_t s);
 int build_schedule(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int smax,
                    TriSchedule &out, hipStream_t s, const Device &dev);
+int build_row_groups(const int64_t *rp, const int32_t *ci, int64_t n, int gmax, DevBuf &gptr, int64_t *ngroups,
+                     hipStream_t s);
 int row_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int32_t *level,
                int32_t *perm, int32_t *level_ptr, int64_t *nlev_host, hipStream_t s,
                const Device &dev);
@@ -160,33 +169,43 @@ int ic0_factor_levels(const int64_t *lrp, const int32_t *lci, double *lv, const 
 int ic0_max_row();
 int spmv_default_slots(int R);
 
+// partials/cols non-null: fused p^T w reduction and alpha update (active must
+// then point at the solve's SolveFlags); active (nullable) as for trsv.
 int spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x,
-         double *y, int R, int slots, hipStream_t s,
-         // optional fused p.w reduction (nullptr: none)
-         double *partials, unsigned *counter, ColState *cols, int64_t max_iter, int mode);
+         double *y, int R, int slots, hipStream_t s, double *partials = nullptr,
+         ColState *cols = nullptr, const int *active = nullptr);
 
+int spmv_grouped(const int64_t *rp, const int32_t *ci, const double *v, int64_t ngroups, const int32_t *gptr,
+                 const double *x, double *y, int R, int slots, hipStream_t s, double *partials = nullptr,
+                 ColState *cols = nullptr, const int *active = nullptr);
+int spmv_grouped_default_slots(int R);
+
+// active (nullable): the solve's count of iterating columns; when it reads 0
+// the launch returns at once (steps queued past convergence cost a launch).
 int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *out, int R,
-         int64_t ld, hipStream_t s, const Device &dev, int *err);
+         int64_t ld, hipStream_t s, const Device &dev, int *err, const int *active = nullptr);
 
 int prec_dL(const icpcg_prec *P, const void *Z, const void *Yb, const void *Rb, const void *Y,
             void *dL, int R, hipStream_t s);
 
-// PCG vector steps (vec.hip)
-enum ReduceMode { RED_NONE = 0, RED_PW = 1 };
+// PCG vector steps (vec.hip); each reduction is a compute kernel plus a
+// one-block finalize kernel.
 int pcg_init(int64_t n, int R, const double *B, const double *W, double *r, double *p,
-             void *y, void *z, bool f32, double rtol, double *partials, unsigned *counter,
-             ColState *cols, int64_t max_iter, int max_replace, SolveFlags *flags, hipStream_t s);
+             void *y, void *z, bool f32, double rtol, double *partials, ColState *cols,
+             int64_t max_iter, SolveFlags *flags, hipStream_t s);
 int pcg_zero_x(int64_t n, int R, double *X, const ColState *cols, hipStream_t s);
 int pcg_dot_rz(int64_t n, int R, const double *r, const void *z, bool f32, double *partials,
-               unsigned *counter, ColState *cols, SolveFlags *flags, hipStream_t s);
+               ColState *cols, SolveFlags *flags, hipStream_t s);
 int pcg_update_p(int64_t n, int R, const void *z, bool f32, double *p, void *y, void *zf,
-                 const ColState *cols, hipStream_t s);
+                 const ColState *cols, const SolveFlags *flags, hipStream_t s);
+int pcg_pw_finalize(int R, const double *partials, int nb, ColState *cols, const SolveFlags *flags,
+                    hipStream_t s);
 int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const double *w,
-                  double *partials, unsigned *counter, ColState *cols, int64_t max_iter,
-                  SolveFlags *flags, hipStream_t s);
+                  double *partials, ColState *cols, int64_t max_iter, SolveFlags *flags,
+                  hipStream_t s);
 int pcg_true_residual(int64_t n, int R, const double *B, double *W, double *partials,
-                      unsigned *counter, ColState *cols, int64_t max_iter, int max_replace,
-                      int final_pass, SolveFlags *flags, hipStream_t s);
+                      ColState *cols, int64_t max_iter, int max_replace, int final_pass,
+                      SolveFlags *flags, hipStream_t s);
 int pcg_replace_r(int64_t n, int R, const double *W, double *r, ColState *cols, hipStream_t s);
 int gather_cols(int64_t n, int R, const double *src, int64_t lds, int64_t c0, int nc, double *dst,
                 hipStream_t s);

@@ -1,8 +1,10 @@
-// Deterministic grid-wide reduction for R-column blocks: each 256-thread block
-// folds its threads' partials per column in a fixed tree, writes them to a
-// partials buffer, and the last block to arrive (ticket counter) folds the
-// blocks' partials in block order. The result depends only on the grid shape,
-// never on scheduling.
+// Deterministic grid-wide reductions for R-column blocks in two launches:
+// every 256-thread block folds its threads' partials per column in a fixed
+// tree and writes one partial per (block, quantity, column); a one-block
+// finalize kernel then folds the partials in block order and runs the
+// per-column finalizer. The kernel boundary makes the partials visible, so no
+// device-scope fence (an L2 write-back on gfx950) is needed per block. The
+// result depends only on the grid shape, never on scheduling.
 #pragma once
 
 #include "internal.hpp"
@@ -26,14 +28,11 @@ __device__ __forceinline__ void block_fold(double *smem) {
   }
 }
 
-// Returns true in the last block only; then out[k * R + c] holds the grid sum
-// of quantity k for column c (out lives in the caller's shared memory).
-// Thread t contributes v[k] to column t % R. Must be called by every thread.
+// Block partials: thread t contributes v[k] to column t % R.
+// partials[(block * K + k) * R + c]. Must be called by every thread.
 template <int R, int K>
-__device__ bool grid_reduce(const double (&v)[K], double *partials, unsigned *counter, double *smem,
-                            double *out) {
+__device__ __forceinline__ void block_partials(const double (&v)[K], double *partials, double *smem) {
   static_assert(kRedBlock % R == 0, "R must divide the block");
-  __shared__ unsigned ticket;
   const int t = threadIdx.x;
 #pragma unroll
   for (int k = 0; k < K; ++k) smem[k * kRedBlock + t] = v[k];
@@ -43,14 +42,30 @@ __device__ bool grid_reduce(const double (&v)[K], double *partials, unsigned *co
 #pragma unroll
     for (int k = 0; k < K; ++k) partials[((int64_t)blockIdx.x * K + k) * R + t] = smem[k * kRedBlock + t];
   }
-  __threadfence();
+}
+
+// Same, for the lane layout where a thread holds CPL consecutive columns
+// starting at ((t % (R / CPL)) * CPL); K = 1.
+template <int R, int CPL>
+__device__ __forceinline__ void block_partials_cpl(const double (&v)[CPL], double *partials, double *smem) {
+  constexpr int LPR = R / CPL;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CPL; ++k) smem[k * kRedBlock + t] = v[k];
   __syncthreads();
-  if (t == 0) ticket = atomicAdd(counter, 1u);
-  __syncthreads();
-  if (ticket != gridDim.x - 1) return false;
-  __threadfence();
+  block_fold<LPR, CPL>(smem);
+  if (t < LPR) {
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) partials[(int64_t)blockIdx.x * R + t * CPL + k] = smem[k * kRedBlock + t];
+  }
+}
+
+// In the one-block finalize kernel: out[k * R + c] = sum over the nb blocks'
+// partials, folded in block order. Must be called by every thread.
+template <int R, int K>
+__device__ __forceinline__ void fold_partials(const double *partials, int nb, double *smem, double *out) {
+  const int t = threadIdx.x;
   const int c = t % R;
-  const int nb = (int)gridDim.x;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double acc = 0.0;
@@ -63,47 +78,10 @@ __device__ bool grid_reduce(const double (&v)[K], double *partials, unsigned *co
 #pragma unroll
     for (int k = 0; k < K; ++k) out[k * R + t] = smem[k * kRedBlock + t];
   }
-  if (t == 0) *counter = 0u;
   __syncthreads();
-  return true;
 }
 
-// Same as grid_reduce<R, 1>, for the lane layout where a thread holds CPL
-// consecutive columns starting at ((t % (R / CPL)) * CPL).
-template <int R, int CPL>
-__device__ bool grid_reduce_cpl(const double (&v)[CPL], double *partials, unsigned *counter, double *smem,
-                                double *out) {
-  constexpr int LPR = R / CPL;
-  __shared__ unsigned ticket;
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CPL; ++k) smem[k * kRedBlock + t] = v[k];
-  __syncthreads();
-  block_fold<LPR, CPL>(smem);
-  if (t < LPR) {
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) partials[(int64_t)blockIdx.x * R + t * CPL + k] = smem[k * kRedBlock + t];
-  }
-  __threadfence();
-  __syncthreads();
-  if (t == 0) ticket = atomicAdd(counter, 1u);
-  __syncthreads();
-  if (ticket != gridDim.x - 1) return false;
-  __threadfence();
-  const int c = t % R;
-  const int nb = (int)gridDim.x;
-  double acc = 0.0;
-  for (int b = t / R; b < nb; b += kRedBlock / R) acc += partials[(int64_t)b * R + c];
-  smem[t] = acc;
-  __syncthreads();
-  block_fold<R, 1>(smem);
-  if (t < R) out[t] = smem[t];
-  if (t == 0) *counter = 0u;
-  __syncthreads();
-  return true;
-}
-
-// Refresh the host-visible counters from the column states (last block only,
+// Refresh the host-visible counters from the column states (finalize kernel,
 // after its finalizer has run).
 template <int R>
 __device__ __forceinline__ void count_flags(const ColState *cols, SolveFlags *flags) {

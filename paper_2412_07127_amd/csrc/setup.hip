@@ -172,6 +172,31 @@ __global__ __launch_bounds__(kBlock) void k_sn_begin(const int64_t *__restrict__
   }
 }
 
+// begin[i] = 1 unless row i has exactly the columns of row i-1 (rows of one
+// 3-DOF node in a stiffness matrix).
+__global__ __launch_bounds__(kBlock) void k_same_begin(const int64_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci, int64_t n,
+                                                       int32_t *__restrict__ begin) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
+  for (int64_t i = w0; i < n; i += nw) {
+    if (i == 0) {
+      if (lane == 0) begin[0] = 1;
+      continue;
+    }
+    const int64_t sp = rp[i - 1], lp = rp[i] - rp[i - 1];
+    const int64_t si = rp[i], li = rp[i + 1] - rp[i];
+    bool ok = li == lp;
+    if (ok) {
+      bool g = true;
+      for (int64_t q = lane; q < li; q += 64) g = g && (ci[si + q] == ci[sp + q]);
+      ok = __ballot(!g) == 0ull;
+    }
+    if (lane == 0) begin[i] = ok ? 0 : 1;
+  }
+}
+
 __global__ void k_begin_key(const int32_t *__restrict__ begin, int64_t n, int32_t *__restrict__ key) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     key[i] = begin[i] ? (int32_t)i : 0;
@@ -411,36 +436,68 @@ int refresh_values(icpcg_prec *P, hipStream_t s) {
 // rows that share their off-block columns (split into pieces of at most smax
 // rows), with the level of each supernode in the quotient dependency graph
 // and the supernodes sorted by (level, id).
+// Runs of rows flagged by begin[] (1 = starts a new run) split into pieces of
+// at most smax rows: ptr[0..count] row ranges, and (optionally) the piece of
+// every row.
+int runs_to_pieces(const int32_t *begin, int64_t n, int smax, DevBuf &ptr, int32_t *piece_of_row, int64_t *count,
+                   hipStream_t s) {
+  int st;
+  DevBuf key, rs, fb, ex, pr;
+  if (key.reserve(n * 4) || rs.reserve(n * 4) || fb.reserve(n * 4) || ex.reserve(n * 4)) return ICPCG_E_NOMEM;
+  if (!piece_of_row) {
+    if (pr.reserve(n * 4)) return ICPCG_E_NOMEM;
+    piece_of_row = pr.as<int32_t>();
+  }
+  const unsigned g = grid_rows(n, kBlock);
+  hipLaunchKernelGGL(k_begin_key, dim3(g), dim3(kBlock), 0, s, begin, n, key.as<int32_t>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  if ((st = scan_inclusive_max_i32(key.as<int32_t>(), rs.as<int32_t>(), n, s))) return st;
+  hipLaunchKernelGGL(k_split, dim3(g), dim3(kBlock), 0, s, begin, rs.as<int32_t>(), n, smax, fb.as<int32_t>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  int32_t np = 0;
+  if ((st = scan_exclusive_i32(fb.as<int32_t>(), ex.as<int32_t>(), n, s, &np))) return st;
+  *count = np;
+  if (ptr.reserve(((size_t)np + 1) * 4)) return ICPCG_E_NOMEM;
+  hipLaunchKernelGGL(k_sn_index, dim3(g), dim3(kBlock), 0, s, fb.as<int32_t>(), ex.as<int32_t>(), n,
+                     ptr.as<int32_t>(), piece_of_row);
+  ICPCG_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_set_last_i32, dim3(1), dim3(1), 0, s, ptr.as<int32_t>(), (int64_t)np, (int32_t)n);
+  ICPCG_HIP_TRY(hipGetLastError());
+  ICPCG_HIP_TRY(hipStreamSynchronize(s));
+  return ICPCG_OK;
+}
+
+// Groups of up to gmax consecutive rows with identical column lists (used by
+// the grouped SpMV, which then reads each column index and gathers each x row
+// once per group).
+int build_row_groups(const int64_t *rp, const int32_t *ci, int64_t n, int gmax, DevBuf &gptr, int64_t *ngroups,
+                     hipStream_t s) {
+  DevBuf begin;
+  if (begin.reserve(n * 4)) return ICPCG_E_NOMEM;
+  hipLaunchKernelGGL(k_same_begin, dim3(grid_rows(n, 4)), dim3(kBlock), 0, s, rp, ci, n, begin.as<int32_t>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  return runs_to_pieces(begin.as<int32_t>(), n, gmax, gptr, nullptr, ngroups, s);
+}
+
+// Supernode schedule of a triangular pattern: maximal runs of consecutive
+// rows that share their off-block columns (split into pieces of at most smax
+// rows), with the level of each supernode in the quotient dependency graph
+// and the supernodes sorted by (level, id).
 int build_schedule(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int smax, TriSchedule &out,
                    hipStream_t s, const Device &dev) {
   int st;
-  DevBuf begin, key, rs, fb, ex, sn_of_row, level, err;
-  if (begin.reserve(n * 4) || key.reserve(n * 4) || rs.reserve(n * 4) || fb.reserve(n * 4) ||
-      ex.reserve(n * 4) || sn_of_row.reserve(n * 4) || err.reserve(4))
-    return ICPCG_E_NOMEM;
+  DevBuf begin, sn_of_row, level, err;
+  if (begin.reserve(n * 4) || sn_of_row.reserve(n * 4) || err.reserve(4)) return ICPCG_E_NOMEM;
   const unsigned gw = grid_rows(n, 4);
   if (upper)
     hipLaunchKernelGGL(k_sn_begin<true>, dim3(gw), dim3(kBlock), 0, s, rp, ci, n, begin.as<int32_t>());
   else
     hipLaunchKernelGGL(k_sn_begin<false>, dim3(gw), dim3(kBlock), 0, s, rp, ci, n, begin.as<int32_t>());
   ICPCG_HIP_TRY(hipGetLastError());
-  const unsigned g = grid_rows(n, kBlock);
-  hipLaunchKernelGGL(k_begin_key, dim3(g), dim3(kBlock), 0, s, begin.as<int32_t>(), n, key.as<int32_t>());
-  ICPCG_HIP_TRY(hipGetLastError());
-  if ((st = scan_inclusive_max_i32(key.as<int32_t>(), rs.as<int32_t>(), n, s))) return st;
-  hipLaunchKernelGGL(k_split, dim3(g), dim3(kBlock), 0, s, begin.as<int32_t>(), rs.as<int32_t>(), n, smax,
-                     fb.as<int32_t>());
-  ICPCG_HIP_TRY(hipGetLastError());
-  int32_t nsn = 0;
-  if ((st = scan_exclusive_i32(fb.as<int32_t>(), ex.as<int32_t>(), n, s, &nsn))) return st;
+  int64_t nsn = 0;
+  if ((st = runs_to_pieces(begin.as<int32_t>(), n, smax, out.sn_ptr, sn_of_row.as<int32_t>(), &nsn, s))) return st;
   out.nsn = nsn;
-  if (out.sn_ptr.reserve((nsn + 1) * 4) || out.sn_order.reserve(nsn * 4) || level.reserve(nsn * 4))
-    return ICPCG_E_NOMEM;
-  hipLaunchKernelGGL(k_sn_index, dim3(g), dim3(kBlock), 0, s, fb.as<int32_t>(), ex.as<int32_t>(), n,
-                     out.sn_ptr.as<int32_t>(), sn_of_row.as<int32_t>());
-  ICPCG_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_set_last_i32, dim3(1), dim3(1), 0, s, out.sn_ptr.as<int32_t>(), (int64_t)nsn, (int32_t)n);
-  ICPCG_HIP_TRY(hipGetLastError());
+  if (out.sn_order.reserve(nsn * 4) || level.reserve(nsn * 4)) return ICPCG_E_NOMEM;
   if ((st = fill_i32(level.as<int32_t>(), -1, nsn, s)) || (st = fill_i32(err.as<int32_t>(), 0, 1, s))) return st;
   if (upper) {
     auto k = k_levels<true, false>;

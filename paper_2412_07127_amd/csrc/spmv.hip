@@ -1,6 +1,6 @@
 // CSR sparse matrix times an R-column block, FP64 (w = A p of supplementary
-// Algorithm 1), with an optional fused, deterministic p^T w reduction that
-// also computes alpha = r^T z / p^T w for the PCG columns.
+// Algorithm 1), with an optional fused p^T w reduction (deterministic block
+// partials; a one-block finalize kernel computes alpha = r^T z / p^T w).
 //
 // Mapping (wave64): a group of SLOTS * R / CPL lanes owns one row; a lane owns
 // CPL = min(R, 4) consecutive columns and strides over the row's entries
@@ -33,8 +33,8 @@ template <int R, int SLOTS, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                  const double *__restrict__ v, int64_t n,
                                                  const double *__restrict__ x, double *__restrict__ y,
-                                                 int64_t chunk, double *partials, unsigned *counter,
-                                                 ColState *cols) {
+                                                 int64_t chunk, double *partials, const int *__restrict__ active) {
+  if (DOT && active && *active == 0) return;
   constexpr int CPL = R >= 4 ? 4 : R;
   constexpr int LPR = R / CPL;
   constexpr int GROUP = SLOTS * LPR;
@@ -43,6 +43,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t *__restrict__ rp,
   constexpr int QD = SpmvDepth<SLOTS>::v;
   const int t = threadIdx.x;
   const int g = t / GROUP, lg = t % GROUP, slot = lg / LPR, c0 = (lg % LPR) * CPL;
+  (void)t;
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int64_t r0 = lb * chunk;
   const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
@@ -89,25 +90,132 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t *__restrict__ rp,
   }
   if (DOT) {
     __shared__ double smem[CPL * kRedBlock];
-    __shared__ double out[R];
-    if (grid_reduce_cpl<R, CPL>(dot, partials, counter, smem, out)) {
-      if (t < R) {
-        ColState &cs = cols[t];
-        if (cs.active) {
-          const double pw = out[t];
-          cs.pw = pw;
-          if (!isfinite(pw)) { cs.status = ICPCG_E_NONFINITE; cs.active = 0; }
-          else if (!(pw > 0.0)) { cs.status = ICPCG_E_BREAKDOWN; cs.active = 0; }
-          else cs.alpha = cs.rz / pw;
+    block_partials_cpl<R, CPL>(dot, partials, smem);
+  }
+}
+
+// Row-group variant: a lane group owns up to GMAX consecutive rows with
+// identical column lists (the rows of one node), reads each column index once
+// and gathers each x row once for all of them.
+template <int R, int SLOTS, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmv_grp(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                     const double *__restrict__ v, int64_t ngroups,
+                                                     const int32_t *__restrict__ gptr, const double *__restrict__ x,
+                                                     double *__restrict__ y, int64_t chunk, double *partials,
+                                                     const int *__restrict__ active) {
+  if (DOT && active && *active == 0) return;
+  constexpr int GMAX = kSupernodeMax;
+  constexpr int CPL = R >= 4 ? 4 : R;
+  constexpr int LPR = R / CPL;
+  constexpr int GROUP = SLOTS * LPR;
+  static_assert(GROUP <= 64 && 64 % GROUP == 0, "group must tile a wave");
+  constexpr int GPB = kBlock / GROUP;
+  constexpr int QD = SpmvDepth<SLOTS>::v;
+  const int t = threadIdx.x;
+  const int g = t / GROUP, lg = t % GROUP, slot = lg / LPR, c0 = (lg % LPR) * CPL;
+  (void)t;
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t g0 = lb * chunk;
+  const int64_t g1 = g0 + chunk < ngroups ? g0 + chunk : ngroups;
+  double dot[CPL];
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) dot[cc] = 0.0;
+  for (int64_t gi = g0 + g; gi < g1; gi += GPB) {
+    const int64_t r0 = gptr[gi];
+    const int sz = gptr[gi + 1] - (int)r0;
+    const int64_t base = rp[r0];
+    const int64_t m = rp[r0 + 1] - base;
+    int jj[QD];
+    double vv[QD][GMAX];
+#pragma unroll
+    for (int k = 0; k < QD; ++k) {
+      const int64_t q = slot + k * SLOTS;
+      jj[k] = q < m ? ci[base + q] : 0;
+#pragma unroll
+      for (int u = 0; u < GMAX; ++u)
+        vv[k][u] = (q < m && u < sz) ? v[base + u * m + q] : 0.0;
+    }
+    double acc[GMAX][CPL];
+#pragma unroll
+    for (int u = 0; u < GMAX; ++u)
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) acc[u][cc] = 0.0;
+#pragma unroll
+    for (int k = 0; k < QD; ++k) {
+      const int64_t q = slot + k * SLOTS;
+      if (q < m) {
+        const double *xr = x + (int64_t)jj[k] * R + c0;
+        double xv[CPL];
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) xv[cc] = xr[cc];
+#pragma unroll
+        for (int u = 0; u < GMAX; ++u)
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc) acc[u][cc] += vv[k][u] * xv[cc];
+      }
+    }
+    for (int64_t q = slot + QD * SLOTS; q < m; q += SLOTS) {
+      const double *xr = x + (int64_t)ci[base + q] * R + c0;
+      double xv[CPL];
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) xv[cc] = xr[cc];
+#pragma unroll
+      for (int u = 0; u < GMAX; ++u) {
+        const double vq = u < sz ? v[base + u * m + q] : 0.0;
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) acc[u][cc] += vq * xv[cc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < GMAX; ++u)
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) acc[u][cc] = xor_sum_bits<Log2<LPR>::v, Log2<GROUP>::v>(acc[u][cc]);
+    if (slot == 0) {
+#pragma unroll
+      for (int u = 0; u < GMAX; ++u) {
+        if (u < sz) {
+          const int64_t row = r0 + u;
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc) {
+            y[row * R + c0 + cc] = acc[u][cc];
+            if (DOT) dot[cc] += x[row * R + c0 + cc] * acc[u][cc];
+          }
         }
       }
     }
   }
+  if (DOT) {
+    __shared__ double smem[CPL * kRedBlock];
+    block_partials_cpl<R, CPL>(dot, partials, smem);
+  }
+}
+
+template <int R, int SLOTS>
+int launch_grp(const int64_t *rp, const int32_t *ci, const double *v, int64_t ngroups, const int32_t *gptr,
+               const double *x, double *y, hipStream_t s, double *partials, ColState *cols, const int *active) {
+  constexpr int CPL = R >= 4 ? 4 : R;
+  constexpr int GPB = kBlock / (SLOTS * (R / CPL));
+  int64_t nb = (ngroups + GPB * 8 - 1) / (GPB * 8);
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  const int64_t chunk = (ngroups + nb - 1) / nb;
+  nb = (ngroups + chunk - 1) / chunk;
+  if (nb < 1) nb = 1;
+  if (partials) {
+    hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, rp, ci, v, ngroups, gptr,
+                       x, y, chunk, partials, active);
+    ICPCG_HIP_TRY(hipGetLastError());
+    return pcg_pw_finalize(R, partials, (int)nb, cols, reinterpret_cast<const SolveFlags *>(active), s);
+  }
+  hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, rp, ci, v, ngroups, gptr,
+                     x, y, chunk, nullptr, nullptr);
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
 }
 
 template <int R, int SLOTS>
 int launch(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y,
-           hipStream_t s, double *partials, unsigned *counter, ColState *cols) {
+           hipStream_t s, double *partials, ColState *cols, const int *active) {
   constexpr int CPL = R >= 4 ? 4 : R;
   constexpr int GPB = kBlock / (SLOTS * (R / CPL));
   // about 8 row passes per block, at most 4096 blocks (bounded partials)
@@ -117,12 +225,14 @@ int launch(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, con
   const int64_t chunk = (n + nb - 1) / nb;
   nb = (n + chunk - 1) / chunk;
   if (nb < 1) nb = 1;
-  if (partials)
-    hipLaunchKernelGGL((k_spmv<R, SLOTS, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, rp, ci, v, n, x, y,
-                       chunk, partials, counter, cols);
-  else
-    hipLaunchKernelGGL((k_spmv<R, SLOTS, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, rp, ci, v, n, x, y,
-                       chunk, nullptr, nullptr, nullptr);
+  if (partials) {
+    hipLaunchKernelGGL((k_spmv<R, SLOTS, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, rp, ci, v, n, x, y, chunk,
+                       partials, active);
+    ICPCG_HIP_TRY(hipGetLastError());
+    return pcg_pw_finalize(R, partials, (int)nb, cols, reinterpret_cast<const SolveFlags *>(active), s);
+  }
+  hipLaunchKernelGGL((k_spmv<R, SLOTS, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, rp, ci, v, n, x, y, chunk,
+                     nullptr, nullptr);
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
 }
@@ -131,10 +241,10 @@ int launch(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, con
 
 // slots: entry slots per row (the lanes per row are slots * R / min(R, 4)).
 int spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x, double *y, int R,
-         int slots, hipStream_t s, double *partials, unsigned *counter, ColState *cols, int64_t, int) {
+         int slots, hipStream_t s, double *partials, ColState *cols, const int *active) {
   if (n <= 0) return ICPCG_OK;
 #define ICPCG_SPMV_CASE(RR, SS) \
-  if (R == RR && slots == SS) return launch<RR, SS>(rp, ci, v, n, x, y, s, partials, counter, cols);
+  if (R == RR && slots == SS) return launch<RR, SS>(rp, ci, v, n, x, y, s, partials, cols, active);
   ICPCG_SPMV_CASE(1, 8)
   ICPCG_SPMV_CASE(1, 16)
   ICPCG_SPMV_CASE(1, 32)
@@ -153,6 +263,38 @@ int spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const
 #undef ICPCG_SPMV_CASE
   set_error("spmv: unsupported (R, slots) = (" + std::to_string(R) + ", " + std::to_string(slots) + ")");
   return ICPCG_E_INVALID;
+}
+
+int spmv_grouped(const int64_t *rp, const int32_t *ci, const double *v, int64_t ngroups, const int32_t *gptr,
+                 const double *x, double *y, int R, int slots, hipStream_t s, double *partials, ColState *cols,
+                 const int *active) {
+  if (ngroups <= 0) return ICPCG_OK;
+#define ICPCG_SPMVG_CASE(RR, SS) \
+  if (R == RR && slots == SS) \
+    return launch_grp<RR, SS>(rp, ci, v, ngroups, gptr, x, y, s, partials, cols, active);
+  ICPCG_SPMVG_CASE(1, 16)
+  ICPCG_SPMVG_CASE(1, 32)
+  ICPCG_SPMVG_CASE(2, 16)
+  ICPCG_SPMVG_CASE(2, 32)
+  ICPCG_SPMVG_CASE(4, 16)
+  ICPCG_SPMVG_CASE(4, 32)
+  ICPCG_SPMVG_CASE(8, 8)
+  ICPCG_SPMVG_CASE(8, 16)
+  ICPCG_SPMVG_CASE(8, 32)
+  ICPCG_SPMVG_CASE(16, 4)
+  ICPCG_SPMVG_CASE(16, 8)
+  ICPCG_SPMVG_CASE(16, 16)
+#undef ICPCG_SPMVG_CASE
+  set_error("grouped spmv: unsupported (R, slots) = (" + std::to_string(R) + ", " + std::to_string(slots) + ")");
+  return ICPCG_E_INVALID;
+}
+
+int spmv_grouped_default_slots(int R) {
+  if (const char *e = std::getenv("ICPCG_SPMVG_SLOTS")) {
+    const int v = std::atoi(e);
+    if (v > 0) return v;
+  }
+  return R >= 16 ? 8 : (R == 8 ? 16 : 32);
 }
 
 int spmv_default_slots(int R) {

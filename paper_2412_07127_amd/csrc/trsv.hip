@@ -55,19 +55,24 @@ __device__ __forceinline__ int64_t row_start(int64_t ro0, int u, int m, int sz) 
 }
 
 // Single-lane wait until *p no longer holds the pending pattern, with a short
-// backoff. Returns false when the wall-clock limit was hit.
-template <typename U>
-__device__ __forceinline__ bool poll_one(const U *up, U pending, int *err, long long limit) {
-  if (ld_agent(up) != pending) return true;
+// backoff. Returns the value's bits, or the canonical NaN after raising err
+// when the wall-clock limit was hit.
+template <typename TA>
+__device__ __forceinline__ typename Flag<TA>::U poll_one(const typename Flag<TA>::U *up, int *err,
+                                                          long long limit) {
+  using U = typename Flag<TA>::U;
+  U v = ld_agent(up);
+  if (v != Flag<TA>::kPending) return v;
   const long long t0 = wall_clock64();
   int backoff = 1;
   for (;;) {
     for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(1);
-    if (ld_agent(up) != pending) return true;
+    v = ld_agent(up);
+    if (v != Flag<TA>::kPending) return v;
     if (backoff < 4) backoff <<= 1;
     if (wall_clock64() - t0 > limit) {
       __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
+      return Flag<TA>::kCanonNaN;
     }
   }
 }
@@ -75,7 +80,9 @@ __device__ __forceinline__ bool poll_one(const U *up, U pending, int *err, long 
 template <typename TV, typename TA, typename TR, int R, bool UPPER, int QD>
 __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci, const TV *__restrict__ val,
                                                  const SnItem *__restrict__ sched, int64_t nsn,
-                                                 const TR *__restrict__ rhs, TA *out, int *err, long long limit) {
+                                                 const TR *__restrict__ rhs, TA *out, int *err, long long limit,
+                                                 const int *__restrict__ active) {
+  if (active && *active == 0) return;  // every column of the solve has stopped
   using U = typename Flag<TA>::U;
   constexpr U kPend = Flag<TA>::kPending;
   constexpr int CPL = R >= 4 ? 4 : R;   // columns per lane
@@ -142,25 +149,28 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
     }
     for (;;) {
       bool pend = false;
-      int64_t paddr = 0;
+      int pk = 0, pc = 0;
 #pragma unroll
       for (int k = QD - 1; k >= 0; --k)
 #pragma unroll
         for (int cc = CPL - 1; cc >= 0; --cc)
-          if (xb[k][cc] == kPend) { pend = true; paddr = (int64_t)jj[k] * R + c0 + cc; }
+          if (xb[k][cc] == kPend) { pend = true; pk = k; pc = cc; }
       const unsigned long long mask = __ballot(pend);
       if (!mask) break;
-      const int leader = 63 - __clzll(mask);  // the highest pending lane: the nearest rows sit last
-      bool ok = true;
-      if (lane == leader) ok = poll_one<U>(outb + paddr, kPend, err, limit);
-      if (__ballot(!ok)) {
+      // the highest pending lane waits (the nearest rows sit last) and keeps the value
+      if (lane == 63 - __clzll(mask)) {
+        int jp = 0;
+#pragma unroll
+        for (int k = 0; k < QD; ++k)
+          if (k == pk) jp = jj[k];
+        const U v = poll_one<TA>(outb + (int64_t)jp * R + c0 + pc, err, limit);
 #pragma unroll
         for (int k = 0; k < QD; ++k)
 #pragma unroll
           for (int cc = 0; cc < CPL; ++cc)
-            if (xb[k][cc] == kPend) xb[k][cc] = Flag<TA>::kCanonNaN;
-        break;
+            if (k == pk && cc == pc) xb[k][cc] = v;
       }
+      // load again only what is still pending
 #pragma unroll
       for (int k = 0; k < QD; ++k)
 #pragma unroll
@@ -241,12 +251,16 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
 // Waves the solve keeps resident: all that fit (the static round-robin needs
 // the whole grid resident), or fewer when ICPCG_TRSV_WAVES_PER_CU asks.
 template <typename K>
-int64_t resident_blocks(K kernel, const Device &dev) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) {
-    (void)hipGetLastError();
-    per_cu = 1;
+int64_t resident_blocks(K kernel, const Device &dev, int &cached) {
+  if (cached <= 0) {
+    int q = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, kernel, kBlock, 0) != hipSuccess || q < 1) {
+      (void)hipGetLastError();
+      q = 1;
+    }
+    cached = q;
   }
+  int per_cu = cached;
   if (dev.trsv_waves_per_cu > 0) {
     const int want = (dev.trsv_waves_per_cu + 3) / 4;
     if (want < per_cu) per_cu = want;
@@ -254,34 +268,38 @@ int64_t resident_blocks(K kernel, const Device &dev) {
   return (int64_t)per_cu * dev.num_cu;
 }
 
-template <int R> struct Depth { static constexpr int v = 2; };  // 64 slots: rows up to 128 prefetched
-template <> struct Depth<8> { static constexpr int v = 4; };    // 32 slots
-template <> struct Depth<16> { static constexpr int v = 4; };   // 16 slots
+// Prefetch window (entries per lane): 64 slots x 1, 32 x 2, 16 x 3 cover the
+// 39 shared off-block entries of a 3-DOF elasticity node; longer rows go
+// through the (slower) remainder loop.
+template <int R> struct Depth { static constexpr int v = 1; };
+template <> struct Depth<8> { static constexpr int v = 2; };
+template <> struct Depth<16> { static constexpr int v = 3; };
 
 template <typename TV, typename TA, typename TR, int R, bool UPPER>
 int launch(const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs, TA *out, hipStream_t s,
-           const Device &dev, int *err) {
+           const Device &dev, int *err, const int *active) {
   if (S.nsn == 0) return ICPCG_OK;
   auto k = k_trsv<TV, TA, TR, R, UPPER, Depth<R>::v>;
-  int64_t grid = resident_blocks(k, dev);
+  static int per_cu = 0;  // occupancy of this instantiation (same on every MI355X)
+  int64_t grid = resident_blocks(k, dev, per_cu);
   const int64_t need = (S.nsn + 3) / 4;
   if (need < grid) grid = need;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kBlock), 0, s, ci, val, S.items.as<SnItem>(), S.nsn, rhs, out,
-                     err, dev.wait_ticks);
+                     err, dev.wait_ticks, active);
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
 }
 
 template <typename TV, typename TA, typename TR, bool UPPER>
 int dispatch_r(int R, const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs, TA *out, hipStream_t s,
-               const Device &dev, int *err) {
+               const Device &dev, int *err, const int *active) {
   switch (R) {
-    case 1: return launch<TV, TA, TR, 1, UPPER>(S, ci, val, rhs, out, s, dev, err);
-    case 2: return launch<TV, TA, TR, 2, UPPER>(S, ci, val, rhs, out, s, dev, err);
-    case 4: return launch<TV, TA, TR, 4, UPPER>(S, ci, val, rhs, out, s, dev, err);
-    case 8: return launch<TV, TA, TR, 8, UPPER>(S, ci, val, rhs, out, s, dev, err);
-    case 16: return launch<TV, TA, TR, 16, UPPER>(S, ci, val, rhs, out, s, dev, err);
+    case 1: return launch<TV, TA, TR, 1, UPPER>(S, ci, val, rhs, out, s, dev, err, active);
+    case 2: return launch<TV, TA, TR, 2, UPPER>(S, ci, val, rhs, out, s, dev, err, active);
+    case 4: return launch<TV, TA, TR, 4, UPPER>(S, ci, val, rhs, out, s, dev, err, active);
+    case 8: return launch<TV, TA, TR, 8, UPPER>(S, ci, val, rhs, out, s, dev, err, active);
+    case 16: return launch<TV, TA, TR, 16, UPPER>(S, ci, val, rhs, out, s, dev, err, active);
     default:
       set_error("trsv: unsupported block width " + std::to_string(R));
       return ICPCG_E_INVALID;
@@ -292,37 +310,35 @@ int dispatch_r(int R, const TriSchedule &S, const int32_t *ci, const TV *val, co
 
 // `out` must hold the pending pattern in every entry on entry.
 int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *out, int R, int64_t, hipStream_t s,
-         const Device &dev, int *err) {
+         const Device &dev, int *err, const int *active) {
   const int32_t *ci = upper ? P->uci.as<int32_t>() : P->lci.as<int32_t>();
   const TriSchedule &S = upper ? P->su : P->sl;
   if (P->dtype == ICPCG_F64) {
     const double *v = upper ? P->uval.as<double>() : P->lval.as<double>();
     if (upper)
-      return dispatch_r<double, double, double, true>(R, S, ci, v, (const double *)rhs, (double *)out, s, dev, err);
-    return dispatch_r<double, double, double, false>(R, S, ci, v, (const double *)rhs, (double *)out, s, dev, err);
+      return dispatch_r<double, double, double, true>(R, S, ci, v, (const double *)rhs, (double *)out, s, dev, err, active);
+    return dispatch_r<double, double, double, false>(R, S, ci, v, (const double *)rhs, (double *)out, s, dev, err, active);
   }
   if (P->dtype == ICPCG_F32) {
     const float *v = upper ? P->uval_lo.as<float>() : P->lval_lo.as<float>();
     if (upper) {
       if (rhs_f64)
-        return dispatch_r<float, float, double, true>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev, err);
-      return dispatch_r<float, float, float, true>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err);
+        return dispatch_r<float, float, double, true>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev, err, active);
+      return dispatch_r<float, float, float, true>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err, active);
     }
     if (rhs_f64)
-      return dispatch_r<float, float, double, false>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev, err);
-    return dispatch_r<float, float, float, false>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err);
+      return dispatch_r<float, float, double, false>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev, err, active);
+    return dispatch_r<float, float, float, false>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err, active);
   }
   const unsigned short *v = upper ? P->uval_lo.as<unsigned short>() : P->lval_lo.as<unsigned short>();
   if (upper) {
     if (rhs_f64)
-      return dispatch_r<unsigned short, float, double, true>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev,
-                                                             err);
-    return dispatch_r<unsigned short, float, float, true>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err);
+      return dispatch_r<unsigned short, float, double, true>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev, err, active);
+    return dispatch_r<unsigned short, float, float, true>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err, active);
   }
   if (rhs_f64)
-    return dispatch_r<unsigned short, float, double, false>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev,
-                                                            err);
-  return dispatch_r<unsigned short, float, float, false>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err);
+    return dispatch_r<unsigned short, float, double, false>(R, S, ci, v, (const double *)rhs, (float *)out, s, dev, err, active);
+  return dispatch_r<unsigned short, float, float, false>(R, S, ci, v, (const float *)rhs, (float *)out, s, dev, err, active);
 }
 
 }  // namespace icpcg

@@ -1,12 +1,15 @@
 // Vector steps of the PCG loop (supplementary Algorithm 1) for an R-column
-// block, each fused with the one grid-wide reduction it needs and a per-column
-// finalizer that runs in the last block:
+// block. Each step that needs a grid-wide reduction is a compute kernel that
+// writes per-block partials plus a one-block finalize kernel that folds them in
+// fixed order and updates the per-column state:
 //   init          r = b - A x0, ||b||^2, ||r||^2           -> tolerance, start flags
 //   dot_rz        r^T z                                     -> beta = r_k^T z_k / r_{k-1}^T z_{k-1}
 //   update_p      p = z + beta p (also re-arms y, z as pending for the next solves)
+//   (spmv)        p^T w                                     -> alpha = r^T z / p^T w
 //   update_xr     x += alpha p, r -= alpha w, ||r||^2        -> iteration count, stop test
 //   true_residual b - A x, ||b - A x||^2                     -> accept / replace / give up
 // Converged or failed columns are frozen (their x, r, p are no longer touched).
+// Steps queued after every column stopped return at once (n_active == 0).
 #include "reduce.hpp"
 
 namespace icpcg {
@@ -33,13 +36,13 @@ template <> struct Pending<float> {
   static __device__ __forceinline__ float get() { return bitcast<float>(Flag<float>::kPending); }
 };
 
+// ------------------------------------------------------------------ init
+
 template <int R, typename TZ>
 __global__ __launch_bounds__(kBlock) void k_init(int64_t n, const double *__restrict__ B, const double *__restrict__ W,
                                                  double *__restrict__ r, double *__restrict__ p, TZ *__restrict__ y,
-                                                 TZ *__restrict__ z, double rtol, double *partials, unsigned *counter,
-                                                 ColState *cols, int64_t max_iter, SolveFlags *flags) {
+                                                 TZ *__restrict__ z, double *partials) {
   __shared__ double smem[2 * kRedBlock];
-  __shared__ double out[2 * R];
   double bb = 0.0, rr = 0.0;
   ICPCG_GRID_LOOP(e, n * R) {
     const double b = B[e];
@@ -52,37 +55,44 @@ __global__ __launch_bounds__(kBlock) void k_init(int64_t n, const double *__rest
     rr += ri * ri;
   }
   const double v[2] = {bb, rr};
-  if (grid_reduce<R, 2>(v, partials, counter, smem, out)) {
-    const int t = threadIdx.x;
-    if (t < R) {
-      ColState cs;
-      cs.bb = out[t];
-      cs.rr = out[R + t];
-      cs.tol2 = rtol * rtol * cs.bb;
-      cs.rz = cs.pw = cs.alpha = cs.beta = 0.0;
-      cs.trr = cs.rr;
-      cs.iters = cs.repl = cs.replace = cs.zero_x = 0;
-      cs.status = ICPCG_OK;
-      cs.conv = 0;
-      cs.active = 0;
-      cs.pad = 0;
-      if (cs.bb == 0.0) {
-        cs.zero_x = 1;  // b = 0: x = 0 after 0 iterations
-        cs.rr = cs.trr = 0.0;
-      } else if (!isfinite(cs.rr) || !isfinite(cs.bb)) {
-        cs.status = ICPCG_E_NONFINITE;
-      } else if (cs.rr <= cs.tol2) {
-        cs.conv = 1;
-      } else if (max_iter <= 0) {
-        cs.status = ICPCG_E_MAXITER;
-      } else {
-        cs.active = 1;
-      }
-      cols[t] = cs;
+  block_partials<R, 2>(v, partials, smem);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_init_fin(const double *partials, int nb, double rtol, ColState *cols,
+                                                     int64_t max_iter, SolveFlags *flags) {
+  __shared__ double smem[2 * kRedBlock];
+  __shared__ double out[2 * R];
+  fold_partials<R, 2>(partials, nb, smem, out);
+  const int t = threadIdx.x;
+  if (t < R) {
+    ColState cs;
+    cs.bb = out[t];
+    cs.rr = out[R + t];
+    cs.tol2 = rtol * rtol * cs.bb;
+    cs.rz = cs.pw = cs.alpha = cs.beta = 0.0;
+    cs.trr = cs.rr;
+    cs.iters = cs.repl = cs.replace = cs.zero_x = 0;
+    cs.status = ICPCG_OK;
+    cs.conv = 0;
+    cs.active = 0;
+    cs.pad = 0;
+    if (cs.bb == 0.0) {
+      cs.zero_x = 1;  // b = 0: x = 0 after 0 iterations
+      cs.rr = cs.trr = 0.0;
+    } else if (!isfinite(cs.rr) || !isfinite(cs.bb)) {
+      cs.status = ICPCG_E_NONFINITE;
+    } else if (cs.rr <= cs.tol2) {
+      cs.conv = 1;
+    } else if (max_iter <= 0) {
+      cs.status = ICPCG_E_MAXITER;
+    } else {
+      cs.active = 1;
     }
-    __syncthreads();
-    count_flags<R>(cols, flags);
+    cols[t] = cs;
   }
+  __syncthreads();
+  count_flags<R>(cols, flags);
 }
 
 template <int R>
@@ -92,39 +102,50 @@ __global__ __launch_bounds__(kBlock) void k_zero_x(int64_t n, double *__restrict
   }
 }
 
+// -------------------------------------------------------------- r^T z
+
 template <int R, typename TZ>
 __global__ __launch_bounds__(kBlock) void k_dot_rz(int64_t n, const double *__restrict__ r, const TZ *__restrict__ z,
-                                                   double *partials, unsigned *counter, ColState *cols,
-                                                   SolveFlags *flags) {
+                                                   double *partials, const SolveFlags *flags) {
+  if (flags->n_active == 0) return;
   __shared__ double smem[kRedBlock];
-  __shared__ double out[R];
   double acc = 0.0;
   ICPCG_GRID_LOOP(e, n * R) acc += r[e] * (double)z[e];
   const double v[1] = {acc};
-  if (grid_reduce<R, 1>(v, partials, counter, smem, out)) {
-    const int t = threadIdx.x;
-    if (t < R) {
-      ColState &cs = cols[t];
-      cs.replace = 0;
-      if (cs.active) {
-        const double rz = out[t];
-        if (!isfinite(rz)) { cs.status = ICPCG_E_NONFINITE; cs.active = 0; }
-        else if (!(rz > 0.0)) { cs.status = ICPCG_E_BREAKDOWN; cs.active = 0; }
-        else {
-          cs.beta = cs.iters == 0 ? 0.0 : rz / cs.rz;
-          cs.rz = rz;
-        }
+  block_partials<R, 1>(v, partials, smem);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_rz_fin(const double *partials, int nb, ColState *cols, SolveFlags *flags) {
+  if (flags->n_active == 0) return;
+  __shared__ double smem[kRedBlock];
+  __shared__ double out[R];
+  fold_partials<R, 1>(partials, nb, smem, out);
+  const int t = threadIdx.x;
+  if (t < R) {
+    ColState &cs = cols[t];
+    cs.replace = 0;
+    if (cs.active) {
+      const double rz = out[t];
+      if (!isfinite(rz)) { cs.status = ICPCG_E_NONFINITE; cs.active = 0; }
+      else if (!(rz > 0.0)) { cs.status = ICPCG_E_BREAKDOWN; cs.active = 0; }
+      else {
+        cs.beta = cs.iters == 0 ? 0.0 : rz / cs.rz;
+        cs.rz = rz;
       }
     }
-    __syncthreads();
-    count_flags<R>(cols, flags);
   }
+  __syncthreads();
+  count_flags<R>(cols, flags);
 }
+
+// ------------------------------------------------------------- update p
 
 template <int R, typename TZ>
 __global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, const TZ *__restrict__ z, double *__restrict__ p,
                                                      TZ *__restrict__ y, TZ *__restrict__ zf,
-                                                     const ColState *__restrict__ cols) {
+                                                     const ColState *__restrict__ cols, const SolveFlags *flags) {
+  if (flags->n_active == 0) return;
   __shared__ double beta[R];
   __shared__ int act[R];
   if (threadIdx.x < R) {
@@ -140,13 +161,37 @@ __global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, const TZ *__rest
   }
 }
 
+// ------------------------------------------------------------ p^T w -> alpha
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_pw_fin(const double *partials, int nb, ColState *cols,
+                                                   const SolveFlags *flags) {
+  if (flags->n_active == 0) return;
+  __shared__ double smem[kRedBlock];
+  __shared__ double out[R];
+  fold_partials<R, 1>(partials, nb, smem, out);
+  const int t = threadIdx.x;
+  if (t < R) {
+    ColState &cs = cols[t];
+    if (cs.active) {
+      const double pw = out[t];
+      cs.pw = pw;
+      if (!isfinite(pw)) { cs.status = ICPCG_E_NONFINITE; cs.active = 0; }
+      else if (!(pw > 0.0)) { cs.status = ICPCG_E_BREAKDOWN; cs.active = 0; }
+      else cs.alpha = cs.rz / pw;
+    }
+  }
+}
+
+// --------------------------------------------------------- update x, r
+
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_update_xr(int64_t n, double *__restrict__ X, double *__restrict__ r,
                                                       const double *__restrict__ p, const double *__restrict__ w,
-                                                      double *partials, unsigned *counter, ColState *cols,
-                                                      int64_t max_iter, SolveFlags *flags) {
+                                                      const ColState *__restrict__ cols, double *partials,
+                                                      const SolveFlags *flags) {
+  if (flags->n_active == 0) return;
   __shared__ double smem[kRedBlock];
-  __shared__ double out[R];
   __shared__ double alpha[R];
   __shared__ int act[R];
   if (threadIdx.x < R) {
@@ -165,31 +210,38 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int64_t n, double *__restr
     }
   }
   const double v[1] = {acc};
-  if (grid_reduce<R, 1>(v, partials, counter, smem, out)) {
-    const int t = threadIdx.x;
-    if (t < R) {
-      ColState &cs = cols[t];
-      if (cs.active) {
-        cs.iters += 1;
-        cs.rr = out[t];
-        if (!isfinite(cs.rr)) { cs.status = ICPCG_E_NONFINITE; cs.active = 0; }
-        else if (cs.rr <= cs.tol2) { cs.conv = 1; cs.active = 0; }
-        else if (cs.iters >= max_iter) { cs.status = ICPCG_E_MAXITER; cs.active = 0; }
-      }
-    }
-    __syncthreads();
-    count_flags<R>(cols, flags);
-  }
+  block_partials<R, 1>(v, partials, smem);
 }
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_rr_fin(const double *partials, int nb, ColState *cols, int64_t max_iter,
+                                                   SolveFlags *flags) {
+  if (flags->n_active == 0) return;
+  __shared__ double smem[kRedBlock];
+  __shared__ double out[R];
+  fold_partials<R, 1>(partials, nb, smem, out);
+  const int t = threadIdx.x;
+  if (t < R) {
+    ColState &cs = cols[t];
+    if (cs.active) {
+      cs.iters += 1;
+      cs.rr = out[t];
+      if (!isfinite(cs.rr)) { cs.status = ICPCG_E_NONFINITE; cs.active = 0; }
+      else if (cs.rr <= cs.tol2) { cs.conv = 1; cs.active = 0; }
+      else if (cs.iters >= max_iter) { cs.status = ICPCG_E_MAXITER; cs.active = 0; }
+    }
+  }
+  __syncthreads();
+  count_flags<R>(cols, flags);
+}
+
+// ---------------------------------------------------------- true residual
 
 // W holds A x on entry and b - A x on exit.
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_true_residual(int64_t n, const double *__restrict__ B, double *__restrict__ W,
-                                                          double *partials, unsigned *counter, ColState *cols,
-                                                          int64_t max_iter, int max_replace, int final_pass,
-                                                          SolveFlags *flags) {
+                                                          double *partials) {
   __shared__ double smem[kRedBlock];
-  __shared__ double out[R];
   double acc = 0.0;
   ICPCG_GRID_LOOP(e, n * R) {
     const double t = B[e] - W[e];
@@ -197,32 +249,39 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(int64_t n, const doubl
     acc += t * t;
   }
   const double v[1] = {acc};
-  if (grid_reduce<R, 1>(v, partials, counter, smem, out)) {
-    const int t = threadIdx.x;
-    if (t < R) {
-      ColState &cs = cols[t];
-      cs.trr = out[t];
-      if (!final_pass && cs.conv) {
-        cs.conv = 0;
-        if (cs.trr <= cs.tol2) {
-          // converged: status stays OK
-        } else if (cs.repl < max_replace) {
-          cs.repl += 1;
-          cs.rr = cs.trr;
-          if (cs.iters >= max_iter) {
-            cs.status = ICPCG_E_MAXITER;
-          } else {
-            cs.replace = 1;
-            cs.active = 1;
-          }
+  block_partials<R, 1>(v, partials, smem);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_tr_fin(const double *partials, int nb, ColState *cols, int64_t max_iter,
+                                                   int max_replace, int final_pass, SolveFlags *flags) {
+  __shared__ double smem[kRedBlock];
+  __shared__ double out[R];
+  fold_partials<R, 1>(partials, nb, smem, out);
+  const int t = threadIdx.x;
+  if (t < R) {
+    ColState &cs = cols[t];
+    cs.trr = out[t];
+    if (!final_pass && cs.conv) {
+      cs.conv = 0;
+      if (cs.trr <= cs.tol2) {
+        // converged: status stays OK
+      } else if (cs.repl < max_replace) {
+        cs.repl += 1;
+        cs.rr = cs.trr;
+        if (cs.iters >= max_iter) {
+          cs.status = ICPCG_E_MAXITER;
         } else {
-          cs.status = ICPCG_E_TRUE_RESIDUAL;
+          cs.replace = 1;
+          cs.active = 1;
         }
+      } else {
+        cs.status = ICPCG_E_TRUE_RESIDUAL;
       }
     }
-    __syncthreads();
-    count_flags<R>(cols, flags);
   }
+  __syncthreads();
+  count_flags<R>(cols, flags);
 }
 
 template <int R>
@@ -270,16 +329,17 @@ __global__ void k_fill_pending(T *p, int64_t count) {
   }
 
 int pcg_init(int64_t n, int R, const double *B, const double *W, double *r, double *p, void *y, void *z, bool f32,
-             double rtol, double *partials, unsigned *counter, ColState *cols, int64_t max_iter, int,
-             SolveFlags *flags, hipStream_t s) {
+             double rtol, double *partials, ColState *cols, int64_t max_iter, SolveFlags *flags, hipStream_t s) {
   const unsigned g = vec_grid(n, R);
   if (f32) {
     ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_init<RR, float>), dim3(g), dim3(kBlock), 0, s, n, B, W, r, p, (float *)y,
-                                         (float *)z, rtol, partials, counter, cols, max_iter, flags));
+                                         (float *)z, partials));
   } else {
     ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_init<RR, double>), dim3(g), dim3(kBlock), 0, s, n, B, W, r, p,
-                                         (double *)y, (double *)z, rtol, partials, counter, cols, max_iter, flags));
+                                         (double *)y, (double *)z, partials));
   }
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_init_fin<RR>, dim3(1), dim3(kBlock), 0, s, partials, (int)g, rtol, cols,
+                                       max_iter, flags));
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
 }
@@ -290,47 +350,58 @@ int pcg_zero_x(int64_t n, int R, double *X, const ColState *cols, hipStream_t s)
   return ICPCG_OK;
 }
 
-int pcg_dot_rz(int64_t n, int R, const double *r, const void *z, bool f32, double *partials, unsigned *counter,
-               ColState *cols, SolveFlags *flags, hipStream_t s) {
+int pcg_dot_rz(int64_t n, int R, const double *r, const void *z, bool f32, double *partials, ColState *cols,
+               SolveFlags *flags, hipStream_t s) {
   const unsigned g = vec_grid(n, R);
   if (f32) {
     ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_dot_rz<RR, float>), dim3(g), dim3(kBlock), 0, s, n, r, (const float *)z,
-                                         partials, counter, cols, flags));
+                                         partials, flags));
   } else {
     ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_dot_rz<RR, double>), dim3(g), dim3(kBlock), 0, s, n, r,
-                                         (const double *)z, partials, counter, cols, flags));
+                                         (const double *)z, partials, flags));
   }
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_rz_fin<RR>, dim3(1), dim3(kBlock), 0, s, partials, (int)g, cols, flags));
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
 }
 
 int pcg_update_p(int64_t n, int R, const void *z, bool f32, double *p, void *y, void *zf, const ColState *cols,
-                 hipStream_t s) {
+                 const SolveFlags *flags, hipStream_t s) {
   const unsigned g = vec_grid(n, R);
   if (f32) {
     ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, float>), dim3(g), dim3(kBlock), 0, s, n, (const float *)z, p,
-                                         (float *)y, (float *)zf, cols));
+                                         (float *)y, (float *)zf, cols, flags));
   } else {
     ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, double>), dim3(g), dim3(kBlock), 0, s, n, (const double *)z,
-                                         p, (double *)y, (double *)zf, cols));
+                                         p, (double *)y, (double *)zf, cols, flags));
   }
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
 }
 
-int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const double *w, double *partials,
-                  unsigned *counter, ColState *cols, int64_t max_iter, SolveFlags *flags, hipStream_t s) {
-  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_update_xr<RR>, dim3(vec_grid(n, R)), dim3(kBlock), 0, s, n, X, r, p, w,
-                                       partials, counter, cols, max_iter, flags));
+int pcg_pw_finalize(int R, const double *partials, int nb, ColState *cols, const SolveFlags *flags, hipStream_t s) {
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_pw_fin<RR>, dim3(1), dim3(kBlock), 0, s, partials, nb, cols, flags));
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
 }
 
-int pcg_true_residual(int64_t n, int R, const double *B, double *W, double *partials, unsigned *counter,
-                      ColState *cols, int64_t max_iter, int max_replace, int final_pass, SolveFlags *flags,
-                      hipStream_t s) {
-  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_true_residual<RR>, dim3(vec_grid(n, R)), dim3(kBlock), 0, s, n, B, W,
-                                       partials, counter, cols, max_iter, max_replace, final_pass, flags));
+int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const double *w, double *partials,
+                  ColState *cols, int64_t max_iter, SolveFlags *flags, hipStream_t s) {
+  const unsigned g = vec_grid(n, R);
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_update_xr<RR>, dim3(g), dim3(kBlock), 0, s, n, X, r, p, w, cols, partials,
+                                       flags));
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_rr_fin<RR>, dim3(1), dim3(kBlock), 0, s, partials, (int)g, cols, max_iter,
+                                       flags));
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int pcg_true_residual(int64_t n, int R, const double *B, double *W, double *partials, ColState *cols,
+                      int64_t max_iter, int max_replace, int final_pass, SolveFlags *flags, hipStream_t s) {
+  const unsigned g = vec_grid(n, R);
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_true_residual<RR>, dim3(g), dim3(kBlock), 0, s, n, B, W, partials));
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_tr_fin<RR>, dim3(1), dim3(kBlock), 0, s, partials, (int)g, cols, max_iter,
+                                       max_replace, final_pass, flags));
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
 }

@@ -83,6 +83,42 @@ class CSR:
         return L.Csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr())
 
 
+class Matrix:
+    """A CSR matrix analyzed once for repeated products (row groups of
+    identical column lists). Keeps a reference to the CSR tensors."""
+
+    def __init__(self, ctx: "Context", A: CSR):
+        self.ctx, self.A = ctx, A
+        ctx._bind()
+        h = C.c_void_p()
+        a = A.cstruct()
+        ctx._check(ctx.lib.icpcg_mat_create(ctx.h, C.byref(a), C.byref(h)))
+        self.h = h
+
+    @property
+    def n(self):
+        return self.A.n
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.icpcg_mat_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def spmv(self, X: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self.ctx._bind()
+        R = _block_width(X, self.n, torch.float64)
+        W = torch.empty_like(X) if out is None else out
+        _block_width(W, self.n, torch.float64)
+        self.ctx._check(self.ctx.lib.icpcg_mat_spmv(self.ctx.h, self.h, _ptr(X), _ptr(W), R))
+        return W
+
+
 class Context:
     """An icpcg context bound to the current device; every call runs on
     torch's current stream."""
@@ -156,9 +192,12 @@ class Context:
         self._check(self.lib.icpcg_spmv(self.h, C.byref(a), _ptr(X.contiguous()), _ptr(W), R))
         return W
 
-    def solve(self, A: CSR, P: "Preconditioner", B: torch.Tensor, X0: torch.Tensor | None = None,
+    def matrix(self, A: CSR) -> Matrix:
+        return Matrix(self, A)
+
+    def solve(self, A, P: "Preconditioner", B: torch.Tensor, X0: torch.Tensor | None = None,
               rtol: float = 1e-8, max_iter: int = 0, max_replace: int = 3, block_width: int = 0,
-              check_every: int = 1, raise_on_error: bool = False):
+              check_every: int = 8, raise_on_error: bool = False):
         """PCG (supplementary Algorithm 1) for the columns of B. Returns (X, infos)."""
         self._bind()
         R = _block_width(B, A.n, torch.float64)
@@ -169,8 +208,11 @@ class Context:
             raise ValueError("X0 and B shapes differ")
         opts = L.SolveOpts(rtol, max_iter, max_replace, block_width, check_every, 0)
         infos = (L.ColInfo * R)()
-        a = A.cstruct()
-        st = self.lib.icpcg_solve(self.h, C.byref(a), P.h, _ptr(B), _ptr(X), R, C.byref(opts), infos)
+        if isinstance(A, Matrix):
+            st = self.lib.icpcg_solve_mat(self.h, A.h, P.h, _ptr(B), _ptr(X), R, C.byref(opts), infos)
+        else:
+            a = A.cstruct()
+            st = self.lib.icpcg_solve(self.h, C.byref(a), P.h, _ptr(B), _ptr(X), R, C.byref(opts), infos)
         if st in (L.E_INVALID, L.E_DEVICE, L.E_NOMEM) or (st != 0 and raise_on_error):
             self._check(st)
         out = [dict(iters=i.iters, replacements=i.replacements, status=i.status, relres=i.relres,

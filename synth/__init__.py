@@ -6,9 +6,9 @@ Krylov iteration.
 """
 
 from .elasticity import (  # noqa: F401
-    CONFIGS,
+    WORKLOADS,
     ElasticityProblem,
-    build_config,
+    build_workload,
     q1_elasticity,
     q1_unit_stiffness,
     body_load,

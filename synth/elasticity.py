@@ -37,20 +37,16 @@ import numpy as np
 
 NU = 0.3
 
-# Configurations of the synthetic workloads: element grid E, lognormal sigma of
-# Young's modulus, number of right-hand sides and the seeds. seed_A draws the
-# element moduli, seed_b the right-hand side(s).
-CONFIGS = {
-    0: dict(E=8, sigma=1.0, nrhs=1, rhs="body+noise"),
-    1: dict(E=40, sigma=1.5, nrhs=1, rhs="body+noise"),
-    2: dict(E=48, sigma=1.0, nrhs=8, rhs="normal"),
-    3: dict(E=100, sigma=2.0, nrhs=1, rhs="body+noise"),
-    4: dict(E=150, sigma=1.5, nrhs=16, rhs="traction"),
+# Synthetic workloads by name: element grid E, lognormal sigma of Young's
+# modulus, right-hand sides, and the seeds (seed_A draws the element moduli,
+# seed_b the right-hand side(s)).
+WORKLOADS = {
+    "q1_8": dict(E=8, sigma=1.0, nrhs=1, rhs="body+noise", seed_A=1000, seed_b=2000),
+    "q1_40": dict(E=40, sigma=1.5, nrhs=1, rhs="body+noise", seed_A=1001, seed_b=2001),
+    "q1_48_block8": dict(E=48, sigma=1.0, nrhs=8, rhs="normal", seed_A=1002, seed_b=3000),
+    "q1_100": dict(E=100, sigma=2.0, nrhs=1, rhs="body+noise", seed_A=1003, seed_b=2003),
+    "q1_150_loads16": dict(E=150, sigma=1.5, nrhs=16, rhs="traction", seed_A=1004, seed_b=2004),
 }
-
-
-def seeds_for(index: int) -> tuple[int, int]:
-    return 1000 + index, 2000 + index
 
 
 def expected_sizes(E: int) -> tuple[int, int]:
@@ -285,21 +281,20 @@ def rigid_body_modes(E: int) -> np.ndarray:
     return M
 
 
-def build_config(index: int, with_rhs: bool = True):
-    """Matrix and right-hand side(s) of one of the synthetic workloads.
+def build_workload(name: str, with_rhs: bool = True):
+    """Matrix and right-hand side(s) of a named synthetic workload.
     Returns (ElasticityProblem, B) with B of shape (n,) or (n, nrhs)."""
-    cfg = CONFIGS[index]
-    seed_A, seed_b = seeds_for(index)
-    prob = q1_elasticity(cfg["E"], cfg["sigma"], seed_A)
+    w = WORKLOADS[name]
+    prob = q1_elasticity(w["E"], w["sigma"], w["seed_A"])
     if not with_rhs:
         return prob, None
-    E = cfg["E"]
-    if cfg["rhs"] == "body+noise":
-        B = body_load(E, 0.1, seed_b)
-    elif cfg["rhs"] == "traction":
-        B = traction_loads(E, cfg["nrhs"], seed_b)
-    elif cfg["rhs"] == "normal":
-        B = np.random.default_rng(3000).standard_normal((prob.n, cfg["nrhs"]))
+    E = w["E"]
+    if w["rhs"] == "body+noise":
+        B = body_load(E, 0.1, w["seed_b"])
+    elif w["rhs"] == "traction":
+        B = traction_loads(E, w["nrhs"], w["seed_b"])
+    elif w["rhs"] == "normal":
+        B = np.random.default_rng(w["seed_b"]).standard_normal((prob.n, w["nrhs"]))
     else:
-        raise ValueError(cfg["rhs"])
+        raise ValueError(w["rhs"])
     return prob, B

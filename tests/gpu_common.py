@@ -8,12 +8,12 @@ import functools
 import numpy as np
 
 import oracle
-from synth import build_config, dense_to_csr, laplacian7, q1_elasticity, tridiagonal_spd
+from synth import build_workload, dense_to_csr, laplacian7, q1_elasticity, tridiagonal_spd
 
 
 @functools.lru_cache(maxsize=None)
-def config_problem(idx):
-    prob, b = build_config(idx)
+def workload_problem(name):
+    prob, b = build_workload(name)
     return prob, b
 
 
@@ -49,8 +49,8 @@ def random_lower_pattern(n, density, seed):
 @functools.lru_cache(maxsize=None)
 def named_matrix(key):
     """SPD test matrices by name (CSR numpy triple)."""
-    if key.startswith("cfg"):
-        p, _ = config_problem(int(key[3:]))
+    if key.startswith("w:"):
+        p, _ = workload_problem(key[2:])
         return p.row_ptr, p.col, p.val
     if key.startswith("q1e"):
         E, sigma = key[3:].split("s")

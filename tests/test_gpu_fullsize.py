@@ -1,0 +1,201 @@
+"""Full-size cases in the launch configuration the benchmark times.
+
+The 100^3 elasticity workload (3,060,300 DOF), the 48^3 workload with an
+8-column block (adjoint), and the 150^3 workload (10,260,450 DOF, 16 load
+cases).
+Where the oracle finishes in seconds it is compared element by element
+(factor, level sets, triangular solves, the first PCG iterations, the
+adjoint); converged solves are checked through the true residual computed by
+the oracle's SpMV on the CPU.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2412_07127_amd as pkg
+from gpu_common import relerr
+from synth import body_load, build_workload, q1_elasticity, traction_loads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch.cuda.set_device(0)
+    return pkg.Context()
+
+
+@pytest.fixture(scope="module")
+def q100(ctx):
+    prob, b = build_workload("q1_100")
+    Ah = (prob.row_ptr, prob.col, prob.val)
+    A = pkg.CSR.from_numpy(*Ah)
+    Lg, finfo = ctx.factor(A)
+    st, L, alpha, restarts, _ = oracle.ic0_shifted(*Ah)
+    assert st == oracle.OK
+    U = oracle.transpose(*L)
+    return dict(prob=prob, b=b, Ah=Ah, A=A, Lg=Lg, finfo=finfo, L=L, U=U, alpha=alpha, restarts=restarts)
+
+
+def true_relres(Ah, x, b):
+    return relerr(oracle.spmv(*Ah, x), b)
+
+
+def test_q100_factor_full_parity(q100):
+    assert q100["finfo"]["alpha"] == q100["alpha"] and q100["finfo"]["restarts"] == q100["restarts"]
+    g = q100["Lg"].numpy()
+    L = q100["L"]
+    assert np.array_equal(g[0], L[0]) and np.array_equal(g[1], L[1])
+    scale = np.abs(L[2]).max()
+    assert np.abs(g[2] - L[2]).max() <= 1e-12 * scale
+
+
+def test_q100_levels_and_transpose(ctx, q100):
+    P = ctx.prec(q100["Lg"], "f64")
+    lv = {k: v.cpu().numpy() for k, v in P.levels().items()}
+    L = q100["L"]
+    lev, nl = oracle.levels_lower(L[0], L[1])
+    levu, nlu = oracle.levels_upper(L[0], L[1])
+    assert nl == nlu == 21 * 100 - 9
+    assert np.array_equal(lv["level_L"], lev) and np.array_equal(lv["level_U"], levu)
+    perm, lp = oracle.level_sort(lev, nl)
+    assert np.array_equal(lv["perm_L"], perm) and np.array_equal(lv["level_ptr_L"], lp)
+    # pattern of L^T equals the oracle's; values are the GPU factor's, transposed exactly
+    U = P.transpose().numpy()
+    Ug = oracle.transpose(*q100["Lg"].numpy())
+    for a, b in zip(U, Ug):
+        assert np.array_equal(a, b)
+    assert np.array_equal(U[0], q100["U"][0]) and np.array_equal(U[1], q100["U"][1])
+    info = P.info()
+    assert info["nsn_levels_L"] == info["nsn_levels_U"] == 7 * 100 - 3
+
+
+@pytest.mark.parametrize("R", [1, 16])
+def test_q100_trsv_parity(ctx, q100, R):
+    P = ctx.prec(q100["Lg"], "f64")
+    n = q100["prob"].n
+    Rh = np.random.default_rng(R).standard_normal((n, R))
+    Y = P.trsv(torch.from_numpy(Rh).cuda()).cpu().numpy()
+    Z = P.trsv(torch.from_numpy(Y).cuda(), transpose=True).cpu().numpy()
+    for c in ([0] if R == 1 else [0, 7, 15]):
+        y = oracle.trsv_lower(*q100["L"], Rh[:, c])
+        z = oracle.trsv_upper(*q100["U"], y)
+        assert relerr(Y[:, c], y) <= 1e-12
+        assert relerr(Z[:, c], z) <= 1e-12
+
+
+def test_q100_spmv_block16(ctx, q100):
+    n = q100["prob"].n
+    X = np.random.default_rng(5).standard_normal((n, 16))
+    W = ctx.spmv(q100["A"], torch.from_numpy(X).cuda()).cpu().numpy()
+    for c in (0, 9):
+        ref = oracle.spmv(*q100["Ah"], X[:, c])
+        assert np.abs(W[:, c] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_q100_pcg_first_iterations_match_oracle(ctx, q100):
+    """Same x after the same number of iterations, same factor on both sides.
+    The early iterates of this workload are very sensitive (a 1e-13 relative
+    change of L moves x by ~2e-6 after 25 iterations), so the loop is compared
+    over a few iterations with identical inputs; converged solves are judged by
+    their true residual and against the stored oracle solution."""
+    P = ctx.prec(pkg.CSR.from_numpy(*q100["L"]), "f64")
+    b = q100["b"]
+    k = 5
+    X, info = ctx.solve(q100["A"], P, torch.from_numpy(b).cuda(), rtol=0.0, max_iter=k, max_replace=0)
+    assert info[0]["status"] == pkg._lib.E_MAXITER and info[0]["iters"] == k
+    ref = oracle.pcg(q100["Ah"], q100["L"], q100["U"], b, rtol=0.0, max_iter=k, max_replace=0)
+    assert relerr(X.cpu().numpy(), ref["x"]) <= 1e-10
+
+
+def test_q100_converged_solve_against_stored_oracle(ctx, q100):
+    """Iteration count and sampled solution against the oracle's converged
+    solve (tests/golden/q100_oracle.json, written by make_fullsize_golden.py)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "q100_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle solution not generated")
+    g = json.load(open(path))
+    assert g["alpha"] == q100["alpha"]
+    P = ctx.prec(q100["Lg"], "f64")
+    X, info = ctx.solve(q100["A"], P, torch.from_numpy(q100["b"]).cuda(), rtol=1e-8)
+    k = info[0]["iters"]
+    xs = X.cpu().numpy()[np.asarray(g["sample_index"])]
+    e = relerr(xs, g["x_sample"])
+    print(f"gpu iters {k}, oracle iters {g['iters']}, sampled |x - x_oracle|/|x_oracle| = {e:.2e}")
+    assert abs(k - g["iters"]) <= 1
+    assert e <= 1e-6
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_q100_solve_true_residual(ctx, q100, dt):
+    P = ctx.prec(q100["Lg"], dt)
+    b = q100["b"]
+    X, info = ctx.solve(q100["A"], P, torch.from_numpy(b).cuda(), rtol=1e-8)
+    x = X.cpu().numpy()
+    tr = true_relres(q100["Ah"], x, b)
+    print(f"{dt}: iters {info[0]['iters']} true relres (oracle SpMV) {tr:.3e} "
+          f"(library {info[0]['true_relres']:.3e}) replacements {info[0]['replacements']}")
+    assert info[0]["status"] == 0
+    assert tr <= 1e-8
+    assert abs(tr - info[0]["true_relres"]) <= 1e-3 * tr + 1e-14
+
+
+def test_q100_multi_rhs_16(ctx, q100):
+    P = ctx.prec(q100["Lg"], "f32")
+    B = traction_loads(100, 16, 2004)
+    X, info = ctx.solve(q100["A"], P, torch.from_numpy(B).cuda(), rtol=1e-8)
+    Xh = X.cpu().numpy()
+    assert all(i["status"] == 0 for i in info)
+    for c in (0, 5, 15):
+        assert true_relres(q100["Ah"], Xh[:, c], B[:, c]) <= 1e-8
+    # a column of the batch equals its own single-column solve (same factor)
+    x1, i1 = ctx.solve(q100["A"], P, torch.from_numpy(np.ascontiguousarray(B[:, 5])).cuda(), rtol=1e-8)
+    assert abs(i1[0]["iters"] - info[5]["iters"]) <= 2
+    assert relerr(Xh[:, 5], x1.cpu().numpy()) <= 1e-6
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_q48_adjoint_full_size(ctx, dt):
+    prob, Rh = build_workload("q1_48_block8")   # 48^3 elements, 8 seeded N(0,1) residual columns
+    Ah = (prob.row_ptr, prob.col, prob.val)
+    st, L, alpha, _, _ = oracle.ic0_shifted(*Ah)
+    U = oracle.transpose(*L)
+    A = pkg.CSR.from_numpy(*Ah)
+    P = ctx.prec(pkg.CSR.from_numpy(*L), dt)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    Rt = torch.from_numpy(Rh).cuda()
+    Y, Z = P.apply(Rt.to(tdt))
+    # loss = sum_k ||A z_k - r_k||^2  ->  G = 2 A (A Z - R)
+    Zd = Z.double()
+    G = 2.0 * ctx.spmv(A, (ctx.spmv(A, Zd.contiguous()) - Rt).contiguous())
+    dR, dL = P.apply_backward(G, Y, Z)
+    Gh = G.cpu().numpy()
+    ref = oracle.apply_adjoint(L, U, Rh, Gh)
+    ez = relerr(Zd.cpu().numpy(), ref["Z"])
+    er = relerr(dR.double().cpu().numpy(), ref["Rbar"])
+    el = relerr(dL.double().cpu().numpy(), ref["dL"])
+    print(f"{dt}: Z {ez:.2e} dR {er:.2e} dL {el:.2e}")
+    tol = 1e-10 if dt == "f64" else 1e-3
+    assert ez <= tol and er <= tol and el <= tol
+
+
+def test_q150_multi_rhs_inference_scale(ctx):
+    """150^3 elements (10,260,450 DOF, 820M entries), 16 load cases, FP32 factor."""
+    prob = q1_elasticity(150, 1.5, 1004)
+    Ah = (prob.row_ptr, prob.col, prob.val)
+    A = pkg.CSR.from_numpy(*Ah)
+    Lg, finfo = ctx.factor(A)
+    P = ctx.prec(Lg, "f32")
+    del Lg
+    B = traction_loads(150, 16, 2004)
+    X, info = ctx.solve(A, P, torch.from_numpy(B).cuda(), rtol=1e-8)
+    iters = [i["iters"] for i in info]
+    print(f"q150: alpha {finfo['alpha']} iters {min(iters)}..{max(iters)}")
+    assert all(i["status"] == 0 for i in info)
+    Xh = X.cpu().numpy()
+    for c in (0, 15):
+        assert true_relres(Ah, Xh[:, c], B[:, c]) <= 1e-8

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 import paper_2412_07127_amd as pkg
-from gpu_common import config_problem, named_matrix, oracle_factor, random_lower_pattern, relerr
+from gpu_common import workload_problem, named_matrix, oracle_factor, random_lower_pattern, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -28,7 +28,7 @@ def cols_of(X):
 
 # ---------------------------------------------------------------- SpMV
 
-@pytest.mark.parametrize("key", ["cfg0", "lap7", "q1e3s2.0", "tridiag"])
+@pytest.mark.parametrize("key", ["w:q1_8", "lap7", "q1e3s2.0", "tridiag"])
 @pytest.mark.parametrize("R", [1, 2, 4, 8, 16])
 def test_spmv(ctx, key, R):
     A = named_matrix(key)
@@ -40,9 +40,54 @@ def test_spmv(ctx, key, R):
         assert np.abs(W[:, c] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("key", ["w:q1_8", "lap7", "q1e3s2.0", "grouped_ragged"])
+@pytest.mark.parametrize("R", [1, 2, 4, 8, 16])
+def test_grouped_spmv(ctx, key, R):
+    """Row-group SpMV (analyzed matrix) equals the oracle's row products."""
+    if key == "grouped_ragged":
+        # rows 0-2 share columns, 3 alone, 4-8 share (split into 3 + 2), ragged tail
+        rng = np.random.default_rng(1)
+        n = 301
+        rows, cols = [], []
+        i = 0
+        while i < n:
+            g = min(int(rng.integers(1, 6)), n - i)
+            base = sorted(set(rng.choice(n, size=int(rng.integers(1, 12)), replace=False).tolist()) |
+                          set(range(i, i + g)))
+            for r in range(i, i + g):
+                rows += [r] * len(base)
+                cols += base
+            i += g
+        rp = np.zeros(n + 1, np.int64)
+        np.add.at(rp, np.asarray(rows) + 1, 1)
+        A = (np.cumsum(rp), np.asarray(cols, np.int32), rng.standard_normal(len(cols)))
+    else:
+        A = named_matrix(key)
+    n = A[0].shape[0] - 1
+    M = ctx.matrix(to_gpu(A))
+    X = np.random.default_rng(R).standard_normal((n, R))
+    W = M.spmv(torch.from_numpy(X).cuda()).cpu().numpy()
+    for c in range(R):
+        ref = oracle.spmv(*A, X[:, c])
+        assert np.abs(W[:, c] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
+def test_solve_with_analyzed_matrix(ctx):
+    prob, b = workload_problem("q1_8")
+    Ah = (prob.row_ptr, prob.col, prob.val)
+    M = ctx.matrix(to_gpu(Ah))
+    _, L, U, _ = oracle_factor("w:q1_8")
+    P = ctx.prec(to_gpu(L), "f64")
+    X, info = ctx.solve(M, P, torch.from_numpy(b).cuda(), rtol=1e-8)
+    ref = oracle.pcg(Ah, L, U, b, rtol=1e-8)
+    assert info[0]["status"] == 0 and abs(info[0]["iters"] - ref["iters"]) <= 1
+    same_k = oracle.pcg(Ah, L, U, b, rtol=0.0, max_iter=info[0]["iters"], max_replace=0)
+    assert relerr(X.cpu().numpy(), same_k["x"]) <= 1e-10
+
+
 # -------------------------------------------------------------- levels
 
-LEVEL_CASES = ["cfg0", "q1e5s1.0", "lap7", "tridiag", "diag", "randlow", "one"]
+LEVEL_CASES = ["w:q1_8", "q1e5s1.0", "lap7", "tridiag", "diag", "randlow", "one"]
 
 
 def level_matrix(key):
@@ -91,7 +136,7 @@ def test_supernode_levels_q1():
         assert info["nsn_levels_U"] == 7 * E - 3
 
 
-@pytest.mark.parametrize("key", ["cfg0", "randlow", "tridiag"])
+@pytest.mark.parametrize("key", ["w:q1_8", "randlow", "tridiag"])
 def test_transpose_exact(ctx, key):
     L = level_matrix(key)
     P = ctx.prec(to_gpu(L), "f64")
@@ -103,7 +148,7 @@ def test_transpose_exact(ctx, key):
 
 # ---------------------------------------------------------------- SpTRSV
 
-@pytest.mark.parametrize("key", ["cfg0", "q1e5s2.0", "lap7", "tridiag", "randlow"])
+@pytest.mark.parametrize("key", ["w:q1_8", "q1e5s2.0", "lap7", "tridiag", "randlow"])
 @pytest.mark.parametrize("R", [1, 4, 16])
 def test_trsv_f64(ctx, key, R):
     if key == "randlow":
@@ -125,7 +170,7 @@ def test_trsv_f64(ctx, key, R):
 
 @pytest.mark.parametrize("dt,prec", [("f32", 1), ("bf16", 2)])
 def test_apply_reduced_precision(ctx, dt, prec):
-    A, L, U, _ = oracle_factor("cfg0")
+    A, L, U, _ = oracle_factor("w:q1_8")
     n = L[0].shape[0] - 1
     P = ctx.prec(to_gpu(L), dt)
     r = np.random.default_rng(0).standard_normal(n)
@@ -142,7 +187,7 @@ def test_apply_reduced_precision(ctx, dt, prec):
 
 # ---------------------------------------------------------------- IC(0)
 
-@pytest.mark.parametrize("key", ["cfg0", "q1e5s2.0", "lap7", "tridiag", "kershaw", "cfg1"])
+@pytest.mark.parametrize("key", ["w:q1_8", "q1e5s2.0", "lap7", "tridiag", "kershaw", "w:q1_40"])
 def test_factor(ctx, key):
     A, L, U, alpha = oracle_factor(key)
     Lg, info = ctx.factor(to_gpu(A))
@@ -155,18 +200,18 @@ def test_factor(ctx, key):
 
 # ------------------------------------------------------------------ PCG
 
-@pytest.mark.parametrize("idx", [0, 1])
+@pytest.mark.parametrize("idx", ["q1_8", "q1_40"])
 def test_solve_f64_matches_oracle(ctx, idx):
-    prob, b = config_problem(idx)
+    prob, b = workload_problem(idx)
     Ah = (prob.row_ptr, prob.col, prob.val)
     A = to_gpu(Ah)
     Lg, _ = ctx.factor(A)
     P = ctx.prec(Lg, "f64")
     X, info = ctx.solve(A, P, torch.from_numpy(b).cuda(), rtol=1e-8)
-    _, L, U, _ = oracle_factor(f"cfg{idx}")
+    _, L, U, _ = oracle_factor(f"w:{idx}")
     ref = oracle.pcg(Ah, L, U, b, rtol=1e-8)
     k = info[0]["iters"]
-    print(f"cfg{idx}: gpu iters {k} oracle iters {ref['iters']} true relres {info[0]['true_relres']:.3e}")
+    print(f"{idx}: gpu iters {k} oracle iters {ref['iters']} true relres {info[0]['true_relres']:.3e}")
     assert info[0]["status"] == pkg._lib.OK
     assert abs(k - ref["iters"]) <= 1
     assert info[0]["true_relres"] <= 1e-8
@@ -175,10 +220,10 @@ def test_solve_f64_matches_oracle(ctx, idx):
 
 
 def test_multi_rhs_columns_match_oracle(ctx):
-    prob, _ = config_problem(0)
+    prob, _ = workload_problem("q1_8")
     Ah = (prob.row_ptr, prob.col, prob.val)
     A = to_gpu(Ah)
-    _, L, U, _ = oracle_factor("cfg0")
+    _, L, U, _ = oracle_factor("w:q1_8")
     P = ctx.prec(to_gpu(L), "f64")
     n = prob.n
     B = np.random.default_rng(11).standard_normal((n, 5))
@@ -195,13 +240,13 @@ def test_multi_rhs_columns_match_oracle(ctx):
 
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
 def test_solve_reduced_precision(ctx, dt):
-    prob, b = config_problem(1)
+    prob, b = workload_problem("q1_40")
     Ah = (prob.row_ptr, prob.col, prob.val)
     A = to_gpu(Ah)
     Lg, _ = ctx.factor(A)
     P = ctx.prec(Lg, dt)
     X, info = ctx.solve(A, P, torch.from_numpy(b).cuda(), rtol=1e-8)
-    _, L, U, _ = oracle_factor("cfg1")
+    _, L, U, _ = oracle_factor("w:q1_40")
     ref = oracle.pcg(Ah, L, U, b, rtol=1e-8)
     x = X.cpu().numpy()
     tr = relerr(oracle.spmv(*Ah, x), b)
@@ -239,7 +284,7 @@ def test_adjoint_matches_oracle(ctx, dt):
 # ------------------------------------------------------------ edge cases
 
 def test_zero_rhs_and_exact_start(ctx):
-    prob, b = config_problem(0)
+    prob, b = workload_problem("q1_8")
     A = to_gpu((prob.row_ptr, prob.col, prob.val))
     Lg, _ = ctx.factor(A)
     P = ctx.prec(Lg, "f64")
@@ -254,7 +299,7 @@ def test_zero_rhs_and_exact_start(ctx):
 
 
 def test_max_iter_and_nonfinite(ctx):
-    prob, b = config_problem(0)
+    prob, b = workload_problem("q1_8")
     A = to_gpu((prob.row_ptr, prob.col, prob.val))
     Lg, _ = ctx.factor(A)
     P = ctx.prec(Lg, "f64")

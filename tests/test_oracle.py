@@ -15,7 +15,7 @@ import scipy.sparse as sp
 
 import oracle
 from synth import (banded_spd, dense_spd, dense_to_csr, kershaw4, laplacian7, q1_elasticity,
-                   spectrum_spd, tridiagonal_spd, build_config)
+                   spectrum_spd, tridiagonal_spd, build_workload)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -274,8 +274,8 @@ def test_pcg_zero_rhs_and_exact_start():
     assert res["iters"] == 0
 
 
-def test_pcg_solution_and_residual_config0():
-    prob, b = build_config(0)
+def test_pcg_solution_and_residual_q1_8():
+    prob, b = build_workload("q1_8")
     A = (prob.row_ptr, prob.col, prob.val)
     st, L, alpha, _, _ = oracle.ic0_shifted(*A)
     U = oracle.transpose(*L)
@@ -347,8 +347,8 @@ def test_pcg_iteration_count_convention():
 
 
 @pytest.mark.parametrize("prec", [1, 2])
-def test_pcg_reduced_precision_factor_config0(prec):
-    prob, b = build_config(0)
+def test_pcg_reduced_precision_factor_q1_8(prec):
+    prob, b = build_workload("q1_8")
     A = (prob.row_ptr, prob.col, prob.val)
     st, L, _, _, _ = oracle.ic0_shifted(*A)
     U = oracle.transpose(*L)

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from synth import (body_load, expected_sizes, q1_elasticity, q1_unit_stiffness,
-                   rigid_body_modes, traction_loads, build_config)
+                   rigid_body_modes, traction_loads, build_workload)
 
 
 @pytest.mark.parametrize("E", [1, 2, 3, 5, 8])
@@ -22,8 +22,8 @@ def test_sizes_closed_form(E):
         assert i in c
 
 
-def test_config0_matches_stated_sizes():
-    p, b = build_config(0)
+def test_q1_8_matches_stated_sizes():
+    p, b = build_workload("q1_8")
     assert p.n == 1944 and p.n // 3 == 648 and p.nnz == 123750
     assert b.shape == (1944,)
 
