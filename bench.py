@@ -52,14 +52,54 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_bytes(n, nnzA, nnzL, R, vbytes, rbytes, obytes):
-    """Algorithmic bytes per launch (int32 columns, int64 row pointers):
-    SpMV reads A once (12 B per entry), its row pointers, each x row once and
-    writes y; a triangular solve reads its factor (value + 4 B column), row
-    pointers, the right-hand side once and writes the solution."""
-    spmv = 12 * nnzA + 8 * (n + 1) + 16 * n * R
-    trsv = (vbytes + 4) * nnzL + 8 * (n + 1) + (rbytes + obytes) * n * R
+def grouped_pattern(rp, ci, gmax=3):
+    """Rows grouped as the row-group SpMV reads them (consecutive rows with
+    identical column lists, runs cut into pieces of gmax): returns (number of
+    groups, column indices stored once per group)."""
+    lens = np.diff(rp)
+    n = lens.shape[0]
+    same = np.zeros(n, bool)
+    cand = np.nonzero(lens[1:] == lens[:-1])[0] + 1
+    if cand.size:
+        starts = rp[cand]
+        ln = lens[cand]
+        idx = np.repeat(starts - rp[0], ln) + (np.arange(ln.sum()) - np.repeat(np.cumsum(ln) - ln, ln))
+        eq = ci[idx] == ci[idx - np.repeat(ln, ln)]
+        ok = np.logical_and.reduceat(eq, np.cumsum(ln) - ln) if eq.size else np.zeros(0, bool)
+        same[cand] = ok
+    begin = ~same
+    run_start = np.maximum.accumulate(np.where(begin, np.arange(n), 0))
+    leader = begin | (((np.arange(n) - run_start) % gmax) == 0)
+    return int(leader.sum()), int(lens[leader].sum())
+
+
+def kernel_bytes(n, nnzA, nnzL, nsn, R, vbytes, rbytes, obytes, ngroups, grouped_cols):
+    """Algorithmic bytes per launch (int32 columns, int64 row pointers, each
+    vector row read once): the row-group SpMV reads A's values, the column
+    indices once per row group, the row pointers and group starts, x, and
+    writes y; a triangular solve reads its factor (value + 4 B column), one
+    16-byte schedule record per supernode, the right-hand side, and writes the
+    solution."""
+    spmv = 8 * nnzA + 4 * grouped_cols + 8 * (n + 1) + 4 * (ngroups + 1) + 16 * n * R
+    trsv = (vbytes + 4) * nnzL + 16 * nsn + (rbytes + obytes) * n * R
     return spmv, trsv
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, if the kernel
+    source is unchanged since the counters were taken (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "q1_100_R16_hbm_counters.md")
+    try:
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+        rec = json.loads(m.group(1))[kernel]
+        src = open(os.path.join(ROOT, rec["src"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["src_sha256"]:
+            return None
+        return rec["hbm_bytes"]
+    except (OSError, KeyError, AttributeError, ValueError):
+        return None
 
 
 def time_kernels(ctx, M, P, R, reps, torch):
@@ -223,8 +263,10 @@ def main():
     R = args.nrhs if args.nrhs in (1, 2, 4, 8, 16) else 16
     kt = time_kernels(ctx, M, P32, R, args.kernel_reps, torch)
     n, nnzA, nnzL = prob.n, prob.nnz, Lf.nnz
-    spmv_b, trsvL_b = kernel_bytes(n, nnzA, nnzL, R, 4, 8, 4)
-    _, trsvU_b = kernel_bytes(n, nnzA, nnzL, R, 4, 4, 4)
+    ngroups, gcols = grouped_pattern(prob.row_ptr, prob.col)
+    nsnL, nsnU = pinfo["nsupernodes_L"], pinfo["nsupernodes_U"]
+    spmv_b, trsvL_b = kernel_bytes(n, nnzA, nnzL, nsnL, R, 4, 8, 4, ngroups, gcols)
+    _, trsvU_b = kernel_bytes(n, nnzA, nnzL, nsnU, R, 4, 4, 4, ngroups, gcols)
     kernels = {
         "spmv": dict(s=kt["spmv"], bytes=spmv_b, gbs=spmv_b / kt["spmv"] / 1e9),
         "trsv_L": dict(s=kt["trsv_L"], bytes=trsvL_b, gbs=trsvL_b / kt["trsv_L"] / 1e9),
@@ -234,7 +276,7 @@ def main():
         log(f"kernel {k_}: {v['s'] * 1e3:.3f} ms, {v['gbs']:.0f} GB/s algorithmic")
     dom = max(kernels, key=lambda k_: kernels[k_]["s"])
     roof = dict(bound="hbm", kernel=dom, achieved=round(kernels[dom]["gbs"], 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=round(kernels[dom]["gbs"] / PEAK_HBM_GBS, 4), traffic=None,
+                frac=round(kernels[dom]["gbs"] / PEAK_HBM_GBS, 4), traffic=recorded_traffic(dom),
                 algorithmic_bytes_per_launch=kernels[dom]["bytes"], launch_ms=round(kernels[dom]["s"] * 1e3, 4))
 
     cpu = None
