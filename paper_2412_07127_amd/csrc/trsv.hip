@@ -20,14 +20,15 @@
 //  * Latency: every item's metadata is one 16-byte record in schedule order,
 //    fetched one item ahead; indices, factor values, the diagonal block and
 //    the right-hand side are loaded before any wait; all dependencies are
-//    gathered in one round, and only while some are still pending does a
-//    single lane poll one of them (with a short backoff) before the pending
-//    ones are loaded again, so thousands of waiting waves do not flood the
-//    memory system and a ready input costs one round trip.
-//  * Lanes of a wave are (slot, column group): a lane owns CPL consecutive
-//    columns (CPL = min(R, 4)), R / CPL lanes cover one gathered row of the
-//    row-major block (one contiguous load) and the SLOTS slots stride over the
-//    off-block entries. Partial sums meet in a fixed butterfly (deterministic).
+//    gathered in one round, and only while some are still pending do the
+//    lanes covering one pending row poll its columns (with a short backoff)
+//    before the pending ones are loaded again, so thousands of waiting waves
+//    do not flood the memory system and a ready input costs one round trip.
+//  * Lanes of a wave are (slot, column): R lanes cover one gathered row of
+//    the row-major block, so every device-scope load and every publish is
+//    one contiguous row per instruction (full-line requests, no partial-line
+//    writes), and the 64 / R slots stride over the off-block entries.
+//    Partial sums meet in a fixed butterfly (deterministic).
 //  * Factor values may be FP64, FP32 or bfloat16 (widened to FP32); FP32 and
 //    bfloat16 factors run FP32 arithmetic.
 #include "internal.hpp"
@@ -54,29 +55,6 @@ __device__ __forceinline__ int64_t row_start(int64_t ro0, int u, int m, int sz) 
                : ro0 + (int64_t)u * (m + 1) + (int64_t)u * (u - 1) / 2;
 }
 
-// Single-lane wait until *p no longer holds the pending pattern, with a short
-// backoff. Returns the value's bits, or the canonical NaN after raising err
-// when the wall-clock limit was hit.
-template <typename TA>
-__device__ __forceinline__ typename Flag<TA>::U poll_one(const typename Flag<TA>::U *up, int *err,
-                                                          long long limit) {
-  using U = typename Flag<TA>::U;
-  U v = ld_agent(up);
-  if (v != Flag<TA>::kPending) return v;
-  const long long t0 = wall_clock64();
-  int backoff = 1;
-  for (;;) {
-    for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(1);
-    v = ld_agent(up);
-    if (v != Flag<TA>::kPending) return v;
-    if (backoff < 4) backoff <<= 1;
-    if (wall_clock64() - t0 > limit) {
-      __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return Flag<TA>::kCanonNaN;
-    }
-  }
-}
-
 template <typename TV, typename TA, typename TR, int R, bool UPPER, int QD>
 __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci, const TV *__restrict__ val,
                                                  const SnItem *__restrict__ sched, int64_t nsn,
@@ -85,11 +63,9 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
   if (active && *active == 0) return;  // every column of the solve has stopped
   using U = typename Flag<TA>::U;
   constexpr U kPend = Flag<TA>::kPending;
-  constexpr int CPL = R >= 4 ? 4 : R;   // columns per lane
-  constexpr int LPR = R / CPL;          // lanes per gathered row
-  constexpr int SLOTS = 64 / LPR;       // entry slots per wave
+  constexpr int SLOTS = 64 / R;                  // entry slots per wave; R lanes per gathered row
   constexpr int NDB = kSmax * (kSmax + 1) / 2;  // stored entries of a dense diagonal block
-  const int lane = threadIdx.x & 63, slot = lane / LPR, c0 = (lane % LPR) * CPL;
+  const int lane = threadIdx.x & 63, slot = lane / R, c = lane % R;
   const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
   const U *outb = reinterpret_cast<const U *>(out);
@@ -116,134 +92,121 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
       for (int u = 0; u < kSmax; ++u)
         vv[k][u] = (q < m && u < sz) ? widen<TA>(val[UPPER ? ro[u] + (sz - u) + q : ro[u] + q]) : TA(0);
     }
-    TA dv[NDB];   // diagonal block, row by row (lower: columns a..a+u; upper: a+u..a+sz-1)
-    TA bv[kSmax][CPL];
+    TA dv[NDB];  // diagonal block, row by row (lower: columns a..a+u; upper: a+u..a+sz-1)
+    TA bv[kSmax];
     if (slot == 0) {
 #pragma unroll
       for (int u = 0; u < kSmax; ++u) {
+        if (!UPPER) {
 #pragma unroll
-        for (int w = 0; w < kSmax; ++w) {
-          const int d = u * (u + 1) / 2 + w;  // storage index of (u, w) for w <= u in the lower order
-          if (!UPPER && w <= u) dv[d] = u < sz ? widen<TA>(val[ro[u] + m + w]) : TA(1);
+          for (int w = 0; w <= u; ++w) dv[u * (u + 1) / 2 + w] = u < sz ? widen<TA>(val[ro[u] + m + w]) : TA(1);
+        } else {
+          // row a+u holds columns a+u .. a+sz-1 first: (u, u+w) at u*kSmax - u*(u-1)/2 + w
+#pragma unroll
+          for (int w = 0; w < kSmax - u; ++w)
+            dv[u * kSmax - u * (u - 1) / 2 + w] = (u < sz && w < sz - u) ? widen<TA>(val[ro[u] + w]) : TA(1);
         }
-        if (UPPER) {
-          // row a+u holds columns a+u .. a+sz-1 first: store (u, u+w') at u*kSmax - u*(u-1)/2 + w'
-#pragma unroll
-          for (int w = 0; w < kSmax; ++w) {
-            const int d = u * kSmax - u * (u - 1) / 2 + w;
-            if (w < kSmax - u) dv[d] = (u < sz && w < sz - u) ? widen<TA>(val[ro[u] + w]) : TA(1);
-          }
-        }
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) bv[u][cc] = u < sz ? (TA)rhs[(int64_t)(a + u) * R + c0 + cc] : TA(0);
+        bv[u] = u < sz ? (TA)rhs[(int64_t)(a + u) * R + c] : TA(0);
       }
     }
     // gather the dependencies: one attempt for all, then while any is still
-    // pending one lane polls it and the pending ones are loaded again
-    U xb[QD][CPL];
+    // pending the R lanes covering one pending row poll it together (one
+    // contiguous row per load) and the pending ones are loaded again
+    U xb[QD];
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
       const int q = slot + k * SLOTS;
-#pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) xb[k][cc] = q < m ? ld_agent(outb + (int64_t)jj[k] * R + c0 + cc) : (U)0;
+      xb[k] = q < m ? ld_agent(outb + (int64_t)jj[k] * R + c) : (U)0;
     }
     for (;;) {
       bool pend = false;
-      int pk = 0, pc = 0;
+      int pk = 0;
 #pragma unroll
       for (int k = QD - 1; k >= 0; --k)
-#pragma unroll
-        for (int cc = CPL - 1; cc >= 0; --cc)
-          if (xb[k][cc] == kPend) { pend = true; pk = k; pc = cc; }
+        if (xb[k] == kPend) { pend = true; pk = k; }
       const unsigned long long mask = __ballot(pend);
       if (!mask) break;
-      // the highest pending lane waits (the nearest rows sit last) and keeps the value
-      if (lane == 63 - __clzll(mask)) {
+      const int leader = 63 - __clzll(mask);  // the nearest rows sit last
+      const int pslot = __shfl(slot, leader, ICPCG_WAVE);
+      const int pkk = __shfl(pk, leader, ICPCG_WAVE);
+      if (slot == pslot) {
         int jp = 0;
 #pragma unroll
         for (int k = 0; k < QD; ++k)
-          if (k == pk) jp = jj[k];
-        const U v = poll_one<TA>(outb + (int64_t)jp * R + c0 + pc, err, limit);
+          if (k == pkk) jp = jj[k];
+        const U *p = outb + (int64_t)jp * R + c;
+        U v = ld_agent(p);
+        const long long t0 = wall_clock64();
+        int backoff = 1;
+        while (__ballot(v == kPend) & (((1ull << R) - 1) << (pslot * R))) {
+          for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(1);
+          if (backoff < 4) backoff <<= 1;
+          if (v == kPend) v = ld_agent(p);
+          if (wall_clock64() - t0 > limit) {
+            if (v == kPend) {
+              __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              v = Flag<TA>::kCanonNaN;
+            }
+          }
+        }
 #pragma unroll
         for (int k = 0; k < QD; ++k)
-#pragma unroll
-          for (int cc = 0; cc < CPL; ++cc)
-            if (k == pk && cc == pc) xb[k][cc] = v;
+          if (k == pkk) xb[k] = v;
       }
-      // load again only what is still pending
 #pragma unroll
       for (int k = 0; k < QD; ++k)
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc)
-          if (xb[k][cc] == kPend) xb[k][cc] = ld_agent(outb + (int64_t)jj[k] * R + c0 + cc);
+        if (xb[k] == kPend) xb[k] = ld_agent(outb + (int64_t)jj[k] * R + c);
     }
-    TA acc[kSmax][CPL];
+    TA acc[kSmax];
 #pragma unroll
-    for (int u = 0; u < kSmax; ++u)
-#pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) acc[u][cc] = TA(0);
+    for (int u = 0; u < kSmax; ++u) acc[u] = TA(0);
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
       const int q = slot + k * SLOTS;
       if (q < m) {
+        const TA x = bitcast<TA>(xb[k]);
 #pragma unroll
-        for (int u = 0; u < kSmax; ++u)
-#pragma unroll
-          for (int cc = 0; cc < CPL; ++cc) acc[u][cc] += vv[k][u] * bitcast<TA>(xb[k][cc]);
+        for (int u = 0; u < kSmax; ++u) acc[u] += vv[k][u] * x;
       }
     }
     // rows longer than the prefetch window
     for (int q = slot + QD * SLOTS; q < m; q += SLOTS) {
-      const int j = ci[pcol + q];
-      TA xv[CPL];
+      const TA x = wait_value<TA>(out + (int64_t)ci[pcol + q] * R + c, err, limit);
 #pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) xv[cc] = wait_value<TA>(out + (int64_t)j * R + c0 + cc, err, limit);
-#pragma unroll
-      for (int u = 0; u < kSmax; ++u) {
-        if (u < sz) {
-          const TA v = widen<TA>(val[UPPER ? ro[u] + (sz - u) + q : ro[u] + q]);
-#pragma unroll
-          for (int cc = 0; cc < CPL; ++cc) acc[u][cc] += v * xv[cc];
-        }
-      }
+      for (int u = 0; u < kSmax; ++u)
+        if (u < sz) acc[u] += widen<TA>(val[UPPER ? ro[u] + (sz - u) + q : ro[u] + q]) * x;
     }
 #pragma unroll
-    for (int u = 0; u < kSmax; ++u)
-#pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) acc[u][cc] = xor_sum_hi<Log2<LPR>::v>(acc[u][cc]);
+    for (int u = 0; u < kSmax; ++u) acc[u] = xor_sum_hi<Log2<R>::v>(acc[u]);
     if (slot == 0) {
+      TA xs[kSmax];
+      if (!UPPER) {
 #pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) {
-        const int c = c0 + cc;
-        TA xs[kSmax];
-        if (!UPPER) {
+        for (int u = 0; u < kSmax; ++u) {
+          if (u < sz) {
+            TA sum = bv[u] - acc[u];
 #pragma unroll
-          for (int u = 0; u < kSmax; ++u) {
-            if (u < sz) {
-              TA sum = bv[u][cc] - acc[u][cc];
-#pragma unroll
-              for (int w = 0; w < kSmax; ++w)
-                if (w < u) sum -= dv[u * (u + 1) / 2 + w] * xs[w];
-              xs[u] = sum / dv[u * (u + 1) / 2 + u];
-            }
-          }
-        } else {
-#pragma unroll
-          for (int uu = kSmax - 1; uu >= 0; --uu) {
-            if (uu < sz) {
-              const int base = uu * kSmax - uu * (uu - 1) / 2;  // (uu, uu) in the upper storage
-              TA sum = bv[uu][cc] - acc[uu][cc];
-#pragma unroll
-              for (int w = 0; w < kSmax; ++w)
-                if (w > uu && w < sz) sum -= dv[base + (w - uu)] * xs[w];
-              xs[uu] = sum / dv[base];
-            }
+            for (int w = 0; w < u; ++w) sum -= dv[u * (u + 1) / 2 + w] * xs[w];
+            xs[u] = sum / dv[u * (u + 1) / 2 + u];
           }
         }
+      } else {
 #pragma unroll
-        for (int u = 0; u < kSmax; ++u)
-          if (u < sz) publish_value<TA>(out + (int64_t)(a + u) * R + c, xs[u]);
+        for (int uu = kSmax - 1; uu >= 0; --uu) {
+          if (uu < sz) {
+            const int base = uu * kSmax - uu * (uu - 1) / 2;  // (uu, uu) in the upper storage
+            TA sum = bv[uu] - acc[uu];
+#pragma unroll
+            for (int w = uu + 1; w < kSmax; ++w)
+              if (w < sz) sum -= dv[base + (w - uu)] * xs[w];
+            xs[uu] = sum / dv[base];
+          }
+        }
       }
+      // one contiguous row of R values per store instruction
+#pragma unroll
+      for (int u = 0; u < kSmax; ++u)
+        if (u < sz) publish_value<TA>(out + (int64_t)(a + u) * R + c, xs[u]);
     }
   }
 }
@@ -268,12 +231,10 @@ int64_t resident_blocks(K kernel, const Device &dev, int &cached) {
   return (int64_t)per_cu * dev.num_cu;
 }
 
-// Prefetch window (entries per lane): 64 slots x 1, 32 x 2, 16 x 3 cover the
-// 39 shared off-block entries of a 3-DOF elasticity node; longer rows go
+// Prefetch window (entries per lane) so that SLOTS x depth >= 40 covers the 39
+// shared off-block entries of a 3-DOF elasticity node; longer rows go
 // through the (slower) remainder loop.
-template <int R> struct Depth { static constexpr int v = 1; };
-template <> struct Depth<8> { static constexpr int v = 2; };
-template <> struct Depth<16> { static constexpr int v = 3; };
+template <int R> struct Depth { static constexpr int v = (40 + 64 / R - 1) / (64 / R); };
 
 template <typename TV, typename TA, typename TR, int R, bool UPPER>
 int launch(const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs, TA *out, hipStream_t s,
