@@ -217,10 +217,18 @@ typedef struct {
   double rtol;           /* stop when ||r_k|| <= rtol ||b|| (per column) */
   int64_t max_iter;      /* products A p per column; <= 0: min(n, max(10, 10 sqrt n)) */
   int max_replace;       /* true-residual replacements per column (default 3 when < 0) */
-  int block_width;       /* columns per pass: 0 = autotune, else 1, 2, 4, 8 or 16 */
+  int block_width;       /* columns per pass: 0 = the autotuner's choice (icpcg_autotune),
+                            else 1, 2, 4, 8 or 16. A column's iterates round differently
+                            at different widths (the order of the additions inside a
+                            triangular-solve row follows the lane layout): pass an explicit
+                            width for bitwise-reproducible runs across contexts */
   int check_every;       /* host polls the convergence flags every k steps (<= 0: 8); steps
                             queued after every column stopped return at once */
-  int use_graph;         /* 1: replay the captured step as a hipGraph */
+  int use_graph;         /* 1: the check_every steps between two polls are captured once as a
+                            hipGraph (on a private stream of the context) and replayed; the
+                            graph is kept in the context and reused by later solves while the
+                            operands' pointers, sizes and width are unchanged. Same kernels,
+                            same order, so the same results as use_graph = 0 */
 } icpcg_solve_opts;
 
 typedef struct {
@@ -244,6 +252,25 @@ typedef struct {
 icpcg_status icpcg_solve(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P,
                          const double *B, double *X, int64_t nrhs, const icpcg_solve_opts *opts,
                          icpcg_col_info *info);
+
+typedef struct {
+  int block_width;       /* chosen columns per pass */
+  double ms_per_step[5]; /* measured time of the step's SpMV and two triangular solves at widths
+                            1, 2, 4, 8, 16 (0 where not tried) */
+  double ms_per_rhs;     /* the chosen width's step time per column of the nrhs */
+} icpcg_tune_info;
+
+/* Block-width autotuner for a multi-RHS solve of nrhs columns with (M, P): it
+ * times one step's bandwidth-heavy kernels (both triangular solves with their
+ * re-arming, and the SpMV) at every width w in 1, 2, 4, ... up to the
+ * smallest power of two >= nrhs (at most 16) on the real operands, and picks
+ * the w with the least time for ceil(nrhs / w) passes. The choice is cached in
+ * the context per (operands, nrhs); icpcg_solve with block_width = 0 uses it.
+ * The timing runs on the context's stream and synchronizes it; the
+ * workspace's r, p, w, y and z are overwritten. Errors: ICPCG_E_INVALID,
+ * ICPCG_E_NOMEM, ICPCG_E_DEVICE. */
+icpcg_status icpcg_autotune(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec *P,
+                            int64_t nrhs, icpcg_tune_info *info);
 
 /* icpcg_solve on an analyzed matrix (skips the per-call analysis). */
 icpcg_status icpcg_solve_mat(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec *P,

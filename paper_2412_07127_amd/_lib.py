@@ -51,6 +51,10 @@ class ColInfo(C.Structure):
                 ("relres", C.c_double), ("true_relres", C.c_double)]
 
 
+class TuneInfo(C.Structure):
+    _fields_ = [("block_width", C.c_int), ("ms_per_step", C.c_double * 5), ("ms_per_rhs", C.c_double)]
+
+
 _lib = None
 
 
@@ -90,6 +94,7 @@ def load():
         "icpcg_mat_destroy": ([P], st),
         "icpcg_mat_spmv": ([P, P, P, P, i64], st),
         "icpcg_solve_mat": ([P, P, P, P, P, i64, C.POINTER(SolveOpts), C.POINTER(ColInfo)], st),
+        "icpcg_autotune": ([P, P, P, i64, C.POINTER(TuneInfo)], st),
         "icpcg_version": ([], C.c_char_p),
     }
     for name, (args, res) in sig.items():

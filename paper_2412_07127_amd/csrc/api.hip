@@ -160,6 +160,8 @@ icpcg_status icpcg_create(icpcg_ctx **out, void *stream) {
 icpcg_status icpcg_destroy(icpcg_ctx *ctx) {
   if (!ctx) return ICPCG_OK;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->step_exec) (void)hipGraphExecDestroy(ctx->step_exec);
+  if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   if (ctx->ws.host_flags) (void)hipHostFree(ctx->ws.host_flags);
   delete ctx;
   return ICPCG_OK;
@@ -442,6 +444,71 @@ int spmv_pass(const icpcg_csr *A, const PassBuffers &b, const double *x, double 
   return spmv(A->row_ptr, A->col, A->val, A->n, x, y, R, spmv_default_slots(R), s, partials, cols, active);
 }
 
+// `count` PCG steps of supplementary Algorithm 1 on stream s: z = L^-T L^-1 r,
+// r'z and beta, p = z + beta p, w = A p with p'w, then alpha, x, r and ||r||.
+// Queued steps return at once when no column is active.
+int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const PassBuffers &b, int R,
+                  int64_t max_iter, int count, hipStream_t s) {
+  const int64_t n = A->n;
+  const bool lo = P->dtype != ICPCG_F64;
+  SolveFlags *fl = dev_flags(ctx);
+  int *err = &fl->err;
+  const int *act = &fl->n_active;
+  int st;
+  for (int k = 0; k < count; ++k) {
+    if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err, act))) return st;
+    if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err, act))) return st;
+    if ((st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, b.cols, fl, s))) return st;
+    if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.z, b.cols, fl, s))) return st;
+    if ((st = spmv_pass(A, b, b.p, b.w, R, s, b.partials, b.cols, act))) return st;
+    if ((st = pcg_update_xr(n, R, b.X, b.r, b.p, b.w, b.partials, b.cols, max_iter, fl, s))) return st;
+  }
+  return ICPCG_OK;
+}
+
+// The graph of `count` steps: captured on the context's private stream the
+// first time, then reused while every pointer and size the launches bake in
+// is the same (the values behind the pointers may change freely).
+int step_graph(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const PassBuffers &b, int R,
+               int64_t max_iter, int count, hipGraphExec_t *out) {
+  auto u = [](const void *p) { return (uintptr_t)p; };
+  const std::vector<uintptr_t> key = {
+      u(A->row_ptr), u(A->col), u(A->val), (uintptr_t)A->n, u(b.gptr), (uintptr_t)b.ngroups, u(P),
+      (uintptr_t)P->dtype, u(P->lci.p), u(P->uci.p), u(P->lval.p), u(P->uval.p), u(P->lval_lo.p),
+      u(P->uval_lo.p), u(P->sl.items.p), u(P->su.items.p), (uintptr_t)P->sl.nsn, (uintptr_t)P->su.nsn,
+      u(b.r), u(b.p), u(b.w), u(b.y), u(b.z), u(b.X), u(b.partials), u(b.cols), u(dev_flags(ctx)),
+      (uintptr_t)R, (uintptr_t)max_iter, (uintptr_t)count, (uintptr_t)ctx->dev.wait_ticks,
+      (uintptr_t)ctx->dev.trsv_waves_per_cu, (uintptr_t)spmv_grouped_default_slots(R),
+      (uintptr_t)spmv_default_slots(R)};
+  if (ctx->step_exec && key == ctx->step_key) {
+    *out = ctx->step_exec;
+    return ICPCG_OK;
+  }
+  if (ctx->step_exec) {
+    ICPCG_HIP_TRY(hipGraphExecDestroy(ctx->step_exec));
+    ctx->step_exec = nullptr;
+    ctx->step_key.clear();
+  }
+  if (!ctx->capture) ICPCG_HIP_TRY(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+  ICPCG_HIP_TRY(hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeRelaxed));
+  const int st = enqueue_steps(ctx, A, P, b, R, max_iter, count, ctx->capture);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->capture, &g);
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return host_error(e, "hipStreamEndCapture", __FILE__, __LINE__);
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return host_error(ei, "hipGraphInstantiate", __FILE__, __LINE__);
+  ctx->step_exec = ex;
+  ctx->step_key = key;
+  *out = ex;
+  return ICPCG_OK;
+}
+
 // One block of R columns through supplementary Algorithm 1 with the stop,
 // replacement and failure rules stated in icpcg.h.
 int run_pass(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const PassBuffers &b, int R,
@@ -450,13 +517,14 @@ int run_pass(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const Pass
   const int64_t n = A->n;
   const bool lo = P->dtype != ICPCG_F64;
   SolveFlags *fl = dev_flags(ctx);
-  int *err = &fl->err;
   int st;
   ICPCG_HIP_TRY(hipMemsetAsync(fl, 0, sizeof(SolveFlags), s));
   if ((st = spmv_pass(A, b, b.X, b.w, R, s))) return st;
   if ((st = pcg_init(n, R, b.B, b.w, b.r, b.p, b.y, b.z, lo, o.rtol, b.partials, b.cols, max_iter, fl, s))) return st;
   if ((st = pcg_zero_x(n, R, b.X, b.cols, s))) return st;
   const int every = o.check_every > 0 ? o.check_every : 8;
+  hipGraphExec_t exec = nullptr;
+  if (o.use_graph && (st = step_graph(ctx, A, P, b, R, max_iter, every, &exec))) return st;
   const int64_t guard = max_iter * (int64_t)(o.max_replace + 1) + 16;
   int64_t steps = 0;
   for (;;) {
@@ -477,19 +545,106 @@ int run_pass(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const Pass
       set_error("solve: step guard exceeded");
       return ICPCG_E_DEVICE;
     }
-    for (int k = 0; k < every; ++k, ++steps) {
-      const int *act = &fl->n_active;
-      if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err, act))) return st;
-      if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err, act))) return st;
-      if ((st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, b.cols, fl, s))) return st;
-      if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.z, b.cols, fl, s))) return st;
-      if ((st = spmv_pass(A, b, b.p, b.w, R, s, b.partials, b.cols, act))) return st;
-      if ((st = pcg_update_xr(n, R, b.X, b.r, b.p, b.w, b.partials, b.cols, max_iter, fl, s))) return st;
-    }
+    if (exec)
+      ICPCG_HIP_TRY(hipGraphLaunch(exec, s));
+    else if ((st = enqueue_steps(ctx, A, P, b, R, max_iter, every, s)))
+      return st;
+    steps += every;
   }
   // final true residual of every column (reported)
   if ((st = spmv_pass(A, b, b.X, b.w, R, s))) return st;
   if ((st = pcg_true_residual(n, R, b.B, b.w, b.partials, b.cols, max_iter, o.max_replace, 1, fl, s))) return st;
+  return ICPCG_OK;
+}
+
+}  // namespace
+
+namespace {
+
+int reserve_pass(Workspace &ws, int64_t n, int Rb, bool lo, bool gathered) {
+  const size_t vec8 = (size_t)n * Rb * 8, vecy = (size_t)n * Rb * (lo ? 4 : 8);
+  if (ws.r.reserve(vec8) || ws.p.reserve(vec8) || ws.w.reserve(vec8) || ws.y.reserve(vecy) || ws.z.reserve(vecy) ||
+      ws.partials.reserve((size_t)4096 * Rb * 2 * 8) || ws.cols.reserve(sizeof(ColState) * Rb))
+    return ICPCG_E_NOMEM;
+  if (gathered && (ws.tmp0.reserve(vec8) || ws.tmp1.reserve(vec8))) return ICPCG_E_NOMEM;
+  return ICPCG_OK;
+}
+
+int width_slot(int w) { return w == 1 ? 0 : w == 2 ? 1 : w == 4 ? 2 : w == 8 ? 3 : 4; }
+
+// Block-width autotuner: for each width w up to the smallest power of two
+// >= nrhs (at most 16) it times the bandwidth-heavy part of one PCG step at
+// that width on the real operands (re-arming y and z, both triangular
+// solves, the SpMV) and picks the width with the least time for all nrhs
+// columns, ceil(nrhs / w) passes of it. Decisions are cached per context.
+int tune_width(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec *P, int64_t nrhs, int *width, double ms[5]) {
+  const icpcg_csr *A = &M->A;
+  const int64_t n = A->n;
+  const std::vector<uintptr_t> key = {(uintptr_t)A->row_ptr, (uintptr_t)A->col, (uintptr_t)A->val, (uintptr_t)n,
+                                      (uintptr_t)A->nnz,     (uintptr_t)P,      (uintptr_t)P->dtype,
+                                      (uintptr_t)P->nnz,     (uintptr_t)std::min<int64_t>(nrhs, 1 << 20)};
+  for (const auto &t : ctx->tunes)
+    if (t.key == key) {
+      *width = t.width;
+      for (int i = 0; i < 5; ++i) ms[i] = t.ms[i];
+      return ICPCG_OK;
+    }
+  for (int i = 0; i < 5; ++i) ms[i] = 0.0;
+  int wmax = 1;
+  while (wmax < nrhs && wmax < 16) wmax <<= 1;
+  const bool lo = P->dtype != ICPCG_F64;
+  hipStream_t s = ctx->stream;
+  int st = reserve_pass(ctx->ws, n, wmax, lo, false);
+  if (st) return st;
+  Workspace &ws = ctx->ws;
+  ICPCG_HIP_TRY(hipMemsetAsync(ws.r.p, 0, (size_t)n * wmax * 8, s));
+  ICPCG_HIP_TRY(hipMemsetAsync(ws.p.p, 0, (size_t)n * wmax * 8, s));
+  PassBuffers b{};
+  b.gptr = M->grouped ? M->gptr.as<int32_t>() : nullptr;
+  b.ngroups = M->ngroups;
+  int *err = &dev_flags(ctx)->err;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ICPCG_HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return host_error(hipGetLastError(), "hipEventCreate", __FILE__, __LINE__);
+  }
+  auto one_step = [&](int w) -> int {
+    int r;
+    if ((r = fill_pending(ws.y.p, n * w, lo, s))) return r;
+    if ((r = trsv(P, false, ws.r.p, true, ws.y.p, w, w, s, ctx->dev, err))) return r;
+    if ((r = fill_pending(ws.z.p, n * w, lo, s))) return r;
+    if ((r = trsv(P, true, ws.y.p, !lo, ws.z.p, w, w, s, ctx->dev, err))) return r;
+    return spmv_pass(A, b, ws.p.as<double>(), ws.w.as<double>(), w, s);
+  };
+  constexpr int kReps = 3;
+  double best = 0.0;
+  int best_w = 1;
+  for (int w = 1; w <= wmax && !st; w <<= 1) {
+    if ((st = one_step(w))) break;  // warm-up (code objects, caches)
+    if (hipEventRecord(e0, s) != hipSuccess) { st = host_error(hipGetLastError(), "hipEventRecord", __FILE__, __LINE__); break; }
+    for (int k = 0; k < kReps && !st; ++k) st = one_step(w);
+    if (st) break;
+    float t = 0.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+      st = host_error(hipGetLastError(), "autotune timing", __FILE__, __LINE__);
+      break;
+    }
+    const double step = (double)t / kReps;
+    ms[width_slot(w)] = step;
+    const double total = step * (double)((nrhs + w - 1) / w);
+    if (w == 1 || total < best) {
+      best = total;
+      best_w = w;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  if ((st = take_wait_error(ctx))) return st;
+  ctx->tunes.push_back(icpcg_ctx::Tune{key, best_w, {ms[0], ms[1], ms[2], ms[3], ms[4]}});
+  *width = best_w;
   return ICPCG_OK;
 }
 
@@ -512,20 +667,17 @@ static icpcg_status solve_impl(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_p
     return ICPCG_OK;
   }
   int Rb = o.block_width;
+  if (Rb != 0 && !pow2_width(Rb)) return fail(ctx, ICPCG_E_INVALID, "solve: block_width must be 0, 1, 2, 4, 8 or 16");
   if (Rb == 0) {
-    Rb = 1;
-    while (Rb < nrhs && Rb < 16) Rb <<= 1;
+    double ms[5];
+    const int st = nrhs == 1 ? (Rb = 1, ICPCG_OK) : tune_width(ctx, M, P, nrhs, &Rb, ms);
+    if (st) return finish(ctx, st);
   }
-  if (!pow2_width(Rb)) return fail(ctx, ICPCG_E_INVALID, "solve: block_width must be 0, 1, 2, 4, 8 or 16");
   const bool lo = P->dtype != ICPCG_F64;
   hipStream_t s = ctx->stream;
   Workspace &ws = ctx->ws;
-  const size_t vec8 = (size_t)n * Rb * 8, vecy = (size_t)n * Rb * (lo ? 4 : 8);
   const bool gathered = nrhs != Rb;
-  if (ws.r.reserve(vec8) || ws.p.reserve(vec8) || ws.w.reserve(vec8) || ws.y.reserve(vecy) || ws.z.reserve(vecy) ||
-      ws.partials.reserve((size_t)4096 * Rb * 2 * 8) || ws.cols.reserve(sizeof(ColState) * Rb))
-    return finish(ctx, ICPCG_E_NOMEM);
-  if (gathered && (ws.tmp0.reserve(vec8) || ws.tmp1.reserve(vec8))) return finish(ctx, ICPCG_E_NOMEM);
+  if (reserve_pass(ws, n, Rb, lo, gathered)) return finish(ctx, ICPCG_E_NOMEM);
   int worst = ICPCG_OK;
   std::vector<ColState> hc(Rb);
   for (int64_t c0 = 0; c0 < nrhs; c0 += Rb) {
@@ -615,6 +767,22 @@ extern "C" icpcg_status icpcg_mat_spmv(icpcg_ctx *ctx, const icpcg_mat *M, const
                             ctx->stream));
   return finish(ctx, spmv_grouped(A->row_ptr, A->col, A->val, M->ngroups, M->gptr.as<int32_t>(), X, W, (int)nrhs,
                                   spmv_grouped_default_slots((int)nrhs), ctx->stream));
+}
+
+extern "C" icpcg_status icpcg_autotune(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec *P, int64_t nrhs,
+                                       icpcg_tune_info *info) {
+  if (!ctx || !M || !P || nrhs < 1 || M->A.n != P->n || !info) return fail(ctx, ICPCG_E_INVALID, "autotune: bad arguments");
+  *info = icpcg_tune_info{};
+  if (M->A.n == 0) {
+    info->block_width = 1;
+    return ICPCG_OK;
+  }
+  int w = 1;
+  const int st = tune_width(ctx, M, P, nrhs, &w, info->ms_per_step);
+  if (st) return finish(ctx, st);
+  info->block_width = w;
+  info->ms_per_rhs = info->ms_per_step[width_slot(w)] * (double)((nrhs + w - 1) / w) / (double)nrhs;
+  return ICPCG_OK;
 }
 
 extern "C" icpcg_status icpcg_solve_mat(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec *P, const double *B,

@@ -86,8 +86,17 @@ struct icpcg_ctx {
   icpcg::Device dev;
   icpcg::Workspace ws;
   std::string last_error;
-  // cached autotune decisions keyed by (n, nnz, R)
-  struct Tune { int64_t n, nnz; int R; int spmv_slots; };
+  // PCG steps captured as one graph on a private stream (default priority),
+  // replayed while every launch argument (step_key) is unchanged
+  hipStream_t capture = nullptr;
+  hipGraphExec_t step_exec = nullptr;
+  std::vector<uintptr_t> step_key;
+  // block widths picked by the autotuner, keyed by the operands' identity
+  struct Tune {
+    std::vector<uintptr_t> key;
+    int width;
+    double ms[5];
+  };
   std::vector<Tune> tunes;
 };
 

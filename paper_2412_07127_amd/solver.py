@@ -197,8 +197,11 @@ class Context:
 
     def solve(self, A, P: "Preconditioner", B: torch.Tensor, X0: torch.Tensor | None = None,
               rtol: float = 1e-8, max_iter: int = 0, max_replace: int = 3, block_width: int = 0,
-              check_every: int = 8, raise_on_error: bool = False):
-        """PCG (supplementary Algorithm 1) for the columns of B. Returns (X, infos)."""
+              check_every: int = 8, use_graph: bool = False, raise_on_error: bool = False):
+        """PCG (supplementary Algorithm 1) for the columns of B. Returns (X, infos).
+
+        block_width 0 takes the autotuner's width (see autotune); use_graph
+        replays the steps between two convergence polls as a captured hipGraph."""
         self._bind()
         R = _block_width(B, A.n, torch.float64)
         if P.n != A.n:
@@ -206,7 +209,7 @@ class Context:
         X = torch.zeros_like(B) if X0 is None else X0.clone().contiguous()
         if X.shape != B.shape:
             raise ValueError("X0 and B shapes differ")
-        opts = L.SolveOpts(rtol, max_iter, max_replace, block_width, check_every, 0)
+        opts = L.SolveOpts(rtol, max_iter, max_replace, block_width, check_every, int(bool(use_graph)))
         infos = (L.ColInfo * R)()
         if isinstance(A, Matrix):
             st = self.lib.icpcg_solve_mat(self.h, A.h, P.h, _ptr(B), _ptr(X), R, C.byref(opts), infos)
@@ -218,6 +221,15 @@ class Context:
         out = [dict(iters=i.iters, replacements=i.replacements, status=i.status, relres=i.relres,
                     true_relres=i.true_relres) for i in infos]
         return X, out
+
+    def autotune(self, M: "Matrix", P: "Preconditioner", nrhs: int) -> dict:
+        """Block width for nrhs columns (timed on the operands, cached in the context)."""
+        self._bind()
+        info = L.TuneInfo()
+        self._check(self.lib.icpcg_autotune(self.h, M.h, P.h, int(nrhs), C.byref(info)))
+        return dict(block_width=info.block_width, ms_per_rhs=info.ms_per_rhs,
+                    ms_per_step={w: info.ms_per_step[i] for i, w in enumerate((1, 2, 4, 8, 16))
+                                 if info.ms_per_step[i] > 0})
 
     def sync(self):
         self._check(self.lib.icpcg_sync(self.h))

@@ -1,0 +1,100 @@
+"""Captured PCG steps (hipGraph replay) against eager launches, and the block
+width autotuner, through the C ABI; columns checked against the FP64 oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2412_07127_amd as pkg
+from gpu_common import named_matrix, oracle_factor, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch.cuda.set_device(0)
+    return pkg.Context()
+
+
+def to_gpu(A):
+    return pkg.CSR.from_numpy(*A, device="cuda")
+
+
+def rhs(n, R, seed):
+    B = np.random.default_rng(seed).standard_normal((n, R)) if R > 1 else \
+        np.random.default_rng(seed).standard_normal(n)
+    return torch.from_numpy(B).cuda()
+
+
+def same(a, b):
+    Xa, ia = a
+    Xb, ib = b
+    assert torch.equal(Xa, Xb)
+    assert ia == ib
+
+
+@pytest.mark.parametrize("key,dt,R,width", [("w:q1_8", "f64", 1, 1), ("lap7", "f32", 4, 4),
+                                            ("q1e4s1.5", "bf16", 16, 16), ("w:q1_8", "f64", 5, 4)])
+def test_graph_replay_matches_eager(ctx, key, dt, R, width):
+    A_h, L, _, _ = oracle_factor(key)
+    A = ctx.matrix(to_gpu(A_h))
+    P = ctx.prec(to_gpu(L), dt)
+    B = rhs(A.n, R, 5)
+    kw = dict(rtol=1e-8, block_width=width, check_every=3)
+    eager = ctx.solve(A, P, B, **kw)
+    assert all(i["status"] == 0 for i in eager[1])
+    # other launches between the replays: a product, and a solve whose graph
+    # has other operands (the context then captures again)
+    other = ctx.prec(to_gpu(L), "f64" if dt != "f64" else "f32")
+    for rep in range(3):
+        g = ctx.solve(A, P, B, use_graph=True, **kw)
+        torch.cuda.synchronize()
+        same(g, eager)
+        A.spmv(torch.ones(A.n, dtype=torch.float64, device="cuda"))
+        if rep == 1:
+            ctx.solve(A, other, B, use_graph=True, **kw)
+        torch.cuda.synchronize()
+
+
+def test_graph_replay_stops_like_eager(ctx):
+    A_h, L, _, _ = oracle_factor("w:q1_8")
+    A = ctx.matrix(to_gpu(A_h))
+    P = ctx.prec(to_gpu(L), "f64")
+    B = rhs(A.n, 2, 9)
+    kw = dict(rtol=1e-12, max_iter=7, max_replace=0, block_width=2, check_every=4)
+    eager = ctx.solve(A, P, B, **kw)
+    graph = ctx.solve(A, P, B, use_graph=True, **kw)
+    same(graph, eager)
+    assert [i["iters"] for i in graph[1]] == [7, 7]
+    assert all(i["status"] == pkg._lib.E_MAXITER for i in graph[1])
+    Bh = B.cpu().numpy()
+    for c in range(2):
+        ref = oracle.pcg(A_h, L, oracle.transpose(*L), Bh[:, c], rtol=0.0, max_iter=7, max_replace=0)
+        assert relerr(graph[0][:, c].cpu().numpy(), ref["x"]) <= 1e-10
+
+
+def test_autotune_and_solve(ctx):
+    A_h, L, U, _ = oracle_factor("w:q1_8")
+    A = ctx.matrix(to_gpu(A_h))
+    P = ctx.prec(to_gpu(L), "f64")
+    info = ctx.autotune(A, P, 12)
+    print("autotune:", info)
+    assert info["block_width"] in (1, 2, 4, 8, 16)
+    assert sorted(info["ms_per_step"]) == [1, 2, 4, 8, 16]
+    assert all(v > 0 for v in info["ms_per_step"].values())
+    w = info["block_width"]
+    assert info["ms_per_rhs"] == pytest.approx(info["ms_per_step"][w] * (-(-12 // w)) / 12)
+    assert ctx.autotune(A, P, 12)["block_width"] == w  # cached
+    small = ctx.autotune(A, P, 3)
+    assert sorted(small["ms_per_step"]) == [1, 2, 4]
+    B = rhs(A.n, 12, 21)
+    X, infos = ctx.solve(A, P, B, rtol=1e-8)  # block_width 0: the tuned width
+    Bh, Xh = B.cpu().numpy(), X.cpu().numpy()
+    for c in range(12):
+        k = infos[c]["iters"]
+        ref = oracle.pcg(A_h, L, U, Bh[:, c], rtol=1e-8)
+        assert infos[c]["status"] == 0 and abs(k - ref["iters"]) <= 1
+        same_k = oracle.pcg(A_h, L, U, Bh[:, c], rtol=0.0, max_iter=k, max_replace=0)
+        assert relerr(Xh[:, c], same_k["x"]) <= 1e-10
