@@ -430,7 +430,7 @@ struct PassBuffers {
   void *y, *z;
   double *partials;
   ColState *cols;
-  const int32_t *gptr;  // row groups of A (identical column lists)
+  const SpGroup *grec;  // row groups of A (identical column lists)
   int64_t ngroups;
 };
 
@@ -438,8 +438,8 @@ struct PassBuffers {
 // kernel when groups are available.
 int spmv_pass(const icpcg_csr *A, const PassBuffers &b, const double *x, double *y, int R, hipStream_t s,
               double *partials = nullptr, ColState *cols = nullptr, const int *active = nullptr) {
-  if (b.gptr)
-    return spmv_grouped(A->row_ptr, A->col, A->val, b.ngroups, b.gptr, x, y, R, spmv_grouped_default_slots(R), s,
+  if (b.grec)
+    return spmv_grouped(A->col, A->val, b.ngroups, b.grec, x, y, R, spmv_grouped_default_slots(R), s,
                         partials, cols, active);
   return spmv(A->row_ptr, A->col, A->val, A->n, x, y, R, spmv_default_slots(R), s, partials, cols, active);
 }
@@ -473,7 +473,7 @@ int step_graph(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const Pa
                int64_t max_iter, int count, hipGraphExec_t *out) {
   auto u = [](const void *p) { return (uintptr_t)p; };
   const std::vector<uintptr_t> key = {
-      u(A->row_ptr), u(A->col), u(A->val), (uintptr_t)A->n, u(b.gptr), (uintptr_t)b.ngroups, u(P),
+      u(A->row_ptr), u(A->col), u(A->val), (uintptr_t)A->n, u(b.grec), (uintptr_t)b.ngroups, u(P),
       (uintptr_t)P->dtype, u(P->lci.p), u(P->uci.p), u(P->lval.p), u(P->uval.p), u(P->lval_lo.p),
       u(P->uval_lo.p), u(P->sl.items.p), u(P->su.items.p), (uintptr_t)P->sl.nsn, (uintptr_t)P->su.nsn,
       u(b.r), u(b.p), u(b.w), u(b.y), u(b.z), u(b.X), u(b.partials), u(b.cols), u(dev_flags(ctx)),
@@ -600,7 +600,7 @@ int tune_width(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec *P, int64_t 
   ICPCG_HIP_TRY(hipMemsetAsync(ws.r.p, 0, (size_t)n * wmax * 8, s));
   ICPCG_HIP_TRY(hipMemsetAsync(ws.p.p, 0, (size_t)n * wmax * 8, s));
   PassBuffers b{};
-  b.gptr = M->grouped ? M->gptr.as<int32_t>() : nullptr;
+  b.grec = M->grouped ? M->grec.as<SpGroup>() : nullptr;
   b.ngroups = M->ngroups;
   int *err = &dev_flags(ctx)->err;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -690,7 +690,7 @@ static icpcg_status solve_impl(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_p
     b.z = ws.z.p;
     b.partials = ws.partials.as<double>();
     b.cols = ws.cols.as<ColState>();
-    b.gptr = M->grouped ? M->gptr.as<int32_t>() : nullptr;
+    b.grec = M->grouped ? M->grec.as<SpGroup>() : nullptr;
     b.ngroups = M->ngroups;
     int st;
     if (gathered) {
@@ -733,8 +733,21 @@ int mat_init(icpcg_ctx *ctx, const icpcg_csr *A, icpcg_mat *M) {
   if (A->n == 0) return ICPCG_OK;
   int st = check_matrix(ctx, A, 0);
   if (st) return st;
-  if ((st = build_row_groups(A->row_ptr, A->col, A->n, kSupernodeMax, M->gptr, &M->ngroups, ctx->stream))) return st;
-  M->grouped = M->ngroups < A->n && !std::getenv("ICPCG_NO_ROW_GROUPS");
+  // the group records hold row lengths in 28 bits
+  bool short_rows = A->nnz < (int64_t{1} << 28);
+  if (!short_rows) {
+    DevBuf lens;
+    if (lens.reserve(A->n * 4)) return ICPCG_E_NOMEM;
+    hipLaunchKernelGGL(k_row_len, dim3(256), dim3(256), 0, ctx->stream, A->row_ptr, A->n, lens.as<int32_t>());
+    ICPCG_HIP_TRY(hipGetLastError());
+    int32_t maxlen = 0;
+    if ((st = reduce_max_i32(lens.as<int32_t>(), A->n, ctx->stream, &maxlen))) return st;
+    short_rows = maxlen < (1 << 28);
+  }
+  if (!short_rows || std::getenv("ICPCG_NO_ROW_GROUPS")) return ICPCG_OK;
+  if ((st = build_row_groups(A->row_ptr, A->col, A->n, kSupernodeMax, M->gptr, M->grec, &M->ngroups, ctx->stream)))
+    return st;
+  M->grouped = M->ngroups < A->n;
   return ICPCG_OK;
 }
 }  // namespace
@@ -765,7 +778,7 @@ extern "C" icpcg_status icpcg_mat_spmv(icpcg_ctx *ctx, const icpcg_mat *M, const
   if (!M->grouped)
     return finish(ctx, spmv(A->row_ptr, A->col, A->val, A->n, X, W, (int)nrhs, spmv_default_slots((int)nrhs),
                             ctx->stream));
-  return finish(ctx, spmv_grouped(A->row_ptr, A->col, A->val, M->ngroups, M->gptr.as<int32_t>(), X, W, (int)nrhs,
+  return finish(ctx, spmv_grouped(A->col, A->val, M->ngroups, M->grec.as<SpGroup>(), X, W, (int)nrhs,
                                   spmv_grouped_default_slots((int)nrhs), ctx->stream));
 }
 

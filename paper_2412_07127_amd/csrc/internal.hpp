@@ -122,6 +122,7 @@ struct TriSchedule {
 struct icpcg_mat {
   icpcg_csr A;
   icpcg::DevBuf gptr;   // int32[ngroups + 1] row groups
+  icpcg::DevBuf grec;   // SpGroup[ngroups]
   int64_t ngroups = 0;
   bool grouped = false;
 };
@@ -165,8 +166,18 @@ int build_transpose(icpcg_prec *P, hipStream_t s);
 int refresh_values(icpcg_prec *P, hipStream_t s);
 int build_schedule(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int smax,
                    TriSchedule &out, hipStream_t s, const Device &dev);
-int build_row_groups(const int64_t *rp, const int32_t *ci, int64_t n, int gmax, DevBuf &gptr, int64_t *ngroups,
-                     hipStream_t s);
+// One row group of A for the SpMV: its first row r0, the CSR offset `base`
+// of that row (the group's rows follow at base + u * m) and (m << 3) | size.
+struct SpGroup {
+  int64_t base;
+  int32_t r0;
+  int32_t m_sz;
+};
+
+// Groups of up to gmax consecutive rows with identical column lists (gptr)
+// and their SpGroup records (rows must have fewer than 2^28 entries).
+int build_row_groups(const int64_t *rp, const int32_t *ci, int64_t n, int gmax, DevBuf &gptr, DevBuf &grec,
+                     int64_t *ngroups, hipStream_t s);
 int row_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int32_t *level,
                int32_t *perm, int32_t *level_ptr, int64_t *nlev_host, hipStream_t s,
                const Device &dev);
@@ -184,9 +195,9 @@ int spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const
          double *y, int R, int slots, hipStream_t s, double *partials = nullptr,
          ColState *cols = nullptr, const int *active = nullptr);
 
-int spmv_grouped(const int64_t *rp, const int32_t *ci, const double *v, int64_t ngroups, const int32_t *gptr,
-                 const double *x, double *y, int R, int slots, hipStream_t s, double *partials = nullptr,
-                 ColState *cols = nullptr, const int *active = nullptr);
+int spmv_grouped(const int32_t *ci, const double *v, int64_t ngroups, const SpGroup *grec, const double *x,
+                 double *y, int R, int slots, hipStream_t s, double *partials = nullptr, ColState *cols = nullptr,
+                 const int *active = nullptr);
 int spmv_grouped_default_slots(int R);
 
 // active (nullable): the solve's count of iterating columns; when it reads 0

@@ -470,13 +470,32 @@ int runs_to_pieces(const int32_t *begin, int64_t n, int smax, DevBuf &ptr, int32
 // Groups of up to gmax consecutive rows with identical column lists (used by
 // the grouped SpMV, which then reads each column index and gathers each x row
 // once per group).
-int build_row_groups(const int64_t *rp, const int32_t *ci, int64_t n, int gmax, DevBuf &gptr, int64_t *ngroups,
-                     hipStream_t s) {
+__global__ void k_group_records(const int64_t *__restrict__ rp, const int32_t *__restrict__ gptr, int64_t ngroups,
+                                SpGroup *__restrict__ rec) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r0 = gptr[g];
+    const int64_t base = rp[r0];
+    SpGroup G;
+    G.base = base;
+    G.r0 = r0;
+    G.m_sz = (int32_t)((rp[r0 + 1] - base) << 3) | (gptr[g + 1] - r0);
+    rec[g] = G;
+  }
+}
+
+int build_row_groups(const int64_t *rp, const int32_t *ci, int64_t n, int gmax, DevBuf &gptr, DevBuf &grec,
+                     int64_t *ngroups, hipStream_t s) {
   DevBuf begin;
   if (begin.reserve(n * 4)) return ICPCG_E_NOMEM;
   hipLaunchKernelGGL(k_same_begin, dim3(grid_rows(n, 4)), dim3(kBlock), 0, s, rp, ci, n, begin.as<int32_t>());
   ICPCG_HIP_TRY(hipGetLastError());
-  return runs_to_pieces(begin.as<int32_t>(), n, gmax, gptr, nullptr, ngroups, s);
+  int st = runs_to_pieces(begin.as<int32_t>(), n, gmax, gptr, nullptr, ngroups, s);
+  if (st) return st;
+  if (grec.reserve(*ngroups * sizeof(SpGroup))) return ICPCG_E_NOMEM;
+  hipLaunchKernelGGL(k_group_records, dim3(grid_rows(*ngroups, 4)), dim3(kBlock), 0, s, rp, gptr.as<int32_t>(),
+                     *ngroups, grec.as<SpGroup>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
 }
 
 // Supernode schedule of a triangular pattern: maximal runs of consecutive

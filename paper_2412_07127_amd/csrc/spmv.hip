@@ -2,9 +2,10 @@
 // Algorithm 1), with an optional fused p^T w reduction (deterministic block
 // partials; a one-block finalize kernel computes alpha = r^T z / p^T w).
 //
-// Mapping (wave64): a group of SLOTS * R / CPL lanes owns one row; a lane owns
-// CPL = min(R, 4) consecutive columns and strides over the row's entries
-// slot, slot + SLOTS, ... Each lane first loads the indices and values of up
+// Mapping (wave64): a group of SLOTS * R / CPL lanes owns one row (one row
+// group in the grouped kernel); a lane owns CPL consecutive columns (min(R, 4)
+// in the plain kernel, min(R, 8) in the grouped one) and strides over the
+// row's entries slot, slot + SLOTS, ... Each lane first loads the indices and values of up
 // to QD of its entries, then issues all their x gathers (each one contiguous
 // piece of a row of the row-major block), so every wave keeps many loads in
 // flight. Partial sums meet in a fixed butterfly. Each block owns a
@@ -96,35 +97,41 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t *__restrict__ rp,
 
 // Row-group variant: a lane group owns up to GMAX consecutive rows with
 // identical column lists (the rows of one node), reads each column index once
-// and gathers each x row once for all of them.
-template <int R, int SLOTS, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_spmv_grp(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                     const double *__restrict__ v, int64_t ngroups,
-                                                     const int32_t *__restrict__ gptr, const double *__restrict__ x,
-                                                     double *__restrict__ y, int64_t chunk, double *partials,
+// and gathers each x row once for all of them. Each group's record is loaded
+// one iteration ahead, so a group costs two dependent trips (indices, then x).
+template <int SLOTS> struct GrpDepth {
+  static constexpr int v = (88 + SLOTS - 1) / SLOTS > 11 ? 11 : (88 + SLOTS - 1) / SLOTS;
+};
+
+template <int R, int SLOTS, bool DOT, int CPL, int QD = GrpDepth<SLOTS>::v>
+__global__ __launch_bounds__(kBlock) void k_spmv_grp(const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                     int64_t ngroups, const SpGroup *__restrict__ grec,
+                                                     const double *__restrict__ x, double *__restrict__ y,
+                                                     int64_t chunk, double *partials,
                                                      const int *__restrict__ active) {
   if (DOT && active && *active == 0) return;
   constexpr int GMAX = kSupernodeMax;
-  constexpr int CPL = R >= 4 ? 4 : R;
   constexpr int LPR = R / CPL;
   constexpr int GROUP = SLOTS * LPR;
   static_assert(GROUP <= 64 && 64 % GROUP == 0, "group must tile a wave");
   constexpr int GPB = kBlock / GROUP;
-  constexpr int QD = SpmvDepth<SLOTS>::v;
   const int t = threadIdx.x;
   const int g = t / GROUP, lg = t % GROUP, slot = lg / LPR, c0 = (lg % LPR) * CPL;
-  (void)t;
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int64_t g0 = lb * chunk;
   const int64_t g1 = g0 + chunk < ngroups ? g0 + chunk : ngroups;
   double dot[CPL];
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) dot[cc] = 0.0;
+  SpGroup nxt{};
+  if (g0 + g < g1) nxt = grec[g0 + g];
   for (int64_t gi = g0 + g; gi < g1; gi += GPB) {
-    const int64_t r0 = gptr[gi];
-    const int sz = gptr[gi + 1] - (int)r0;
-    const int64_t base = rp[r0];
-    const int64_t m = rp[r0 + 1] - base;
+    const SpGroup G = nxt;
+    if (gi + GPB < g1) nxt = grec[gi + GPB];
+    const int64_t r0 = G.r0;
+    const int sz = G.m_sz & 7;
+    const int64_t base = G.base;
+    const int64_t m = G.m_sz >> 3;
     int jj[QD];
     double vv[QD][GMAX];
 #pragma unroll
@@ -190,10 +197,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_grp(const int64_t *__restrict__
   }
 }
 
-template <int R, int SLOTS>
-int launch_grp(const int64_t *rp, const int32_t *ci, const double *v, int64_t ngroups, const int32_t *gptr,
-               const double *x, double *y, hipStream_t s, double *partials, ColState *cols, const int *active) {
-  constexpr int CPL = R >= 4 ? 4 : R;
+template <int R, int SLOTS, int CPL>
+int launch_grp(const int32_t *ci, const double *v, int64_t ngroups, const SpGroup *grec, const double *x, double *y,
+               hipStream_t s, double *partials, ColState *cols, const int *active) {
   constexpr int GPB = kBlock / (SLOTS * (R / CPL));
   int64_t nb = (ngroups + GPB * 8 - 1) / (GPB * 8);
   if (nb > 4096) nb = 4096;
@@ -202,13 +208,13 @@ int launch_grp(const int64_t *rp, const int32_t *ci, const double *v, int64_t ng
   nb = (ngroups + chunk - 1) / chunk;
   if (nb < 1) nb = 1;
   if (partials) {
-    hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, rp, ci, v, ngroups, gptr,
-                       x, y, chunk, partials, active);
+    hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, true, CPL>), dim3((unsigned)nb), dim3(kBlock), 0, s, ci, v, ngroups, grec, x,
+                       y, chunk, partials, active);
     ICPCG_HIP_TRY(hipGetLastError());
     return pcg_pw_finalize(R, partials, (int)nb, cols, reinterpret_cast<const SolveFlags *>(active), s);
   }
-  hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, rp, ci, v, ngroups, gptr,
-                     x, y, chunk, nullptr, nullptr);
+  hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, false, CPL>), dim3((unsigned)nb), dim3(kBlock), 0, s, ci, v, ngroups, grec, x,
+                     y, chunk, nullptr, nullptr);
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
 }
@@ -265,25 +271,25 @@ int spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const
   return ICPCG_E_INVALID;
 }
 
-int spmv_grouped(const int64_t *rp, const int32_t *ci, const double *v, int64_t ngroups, const int32_t *gptr,
-                 const double *x, double *y, int R, int slots, hipStream_t s, double *partials, ColState *cols,
-                 const int *active) {
+int spmv_grouped(const int32_t *ci, const double *v, int64_t ngroups, const SpGroup *grec, const double *x,
+                 double *y, int R, int slots, hipStream_t s, double *partials, ColState *cols, const int *active) {
   if (ngroups <= 0) return ICPCG_OK;
+// a lane owns min(R, 8) columns: fewer lanes per row means fewer redundant
+// index and value loads and a shorter butterfly, which outweighs the wider
+// per-lane gathers
 #define ICPCG_SPMVG_CASE(RR, SS) \
   if (R == RR && slots == SS) \
-    return launch_grp<RR, SS>(rp, ci, v, ngroups, gptr, x, y, s, partials, cols, active);
+    return launch_grp<RR, SS, (RR < 8 ? RR : 8)>(ci, v, ngroups, grec, x, y, s, partials, cols, active);
   ICPCG_SPMVG_CASE(1, 16)
   ICPCG_SPMVG_CASE(1, 32)
   ICPCG_SPMVG_CASE(2, 16)
   ICPCG_SPMVG_CASE(2, 32)
   ICPCG_SPMVG_CASE(4, 16)
   ICPCG_SPMVG_CASE(4, 32)
-  ICPCG_SPMVG_CASE(8, 8)
   ICPCG_SPMVG_CASE(8, 16)
   ICPCG_SPMVG_CASE(8, 32)
-  ICPCG_SPMVG_CASE(16, 4)
-  ICPCG_SPMVG_CASE(16, 8)
   ICPCG_SPMVG_CASE(16, 16)
+  ICPCG_SPMVG_CASE(16, 32)
 #undef ICPCG_SPMVG_CASE
   set_error("grouped spmv: unsupported (R, slots) = (" + std::to_string(R) + ", " + std::to_string(slots) + ")");
   return ICPCG_E_INVALID;
@@ -294,7 +300,7 @@ int spmv_grouped_default_slots(int R) {
     const int v = std::atoi(e);
     if (v > 0) return v;
   }
-  return R >= 16 ? 8 : (R == 8 ? 16 : 32);
+  return R >= 8 ? 16 : 32;
 }
 
 int spmv_default_slots(int R) {
