@@ -1,0 +1,181 @@
+"""Pins of the GNN-correction oracle (oracle/gnn.py) against closed forms,
+brute force and finite differences (CPU)."""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import gnn as G
+from synth import dense_to_csr, q1_elasticity
+
+
+def small_graph(E=2, sigma=1.0, seed=5):
+    p = q1_elasticity(E, sigma, seed)
+    A = (p.row_ptr, p.col, p.val)
+    st, L, alpha, restarts, mp = oracle.ic0_shifted(*A)
+    assert st == oracle.OK
+    return A, L, G.Graph(A, L)
+
+
+def dense(rp, ci, val, n):
+    D = np.zeros((n, n))
+    for i in range(n):
+        D[i, ci[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+    return D
+
+
+def pattern(rp, ci, n):
+    B = np.zeros((n, n), bool)
+    for i in range(n):
+        B[i, ci[rp[i]:rp[i + 1]]] = True
+    return B
+
+
+def test_param_count():
+    # 27 (normalization) + 169 + 177 (block 1) + 177 + 177 (block 2) + 177 (block 3)
+    assert G.num_params() == 904
+    th = G.init_params(3)
+    assert np.array_equal(G.pack(G.unpack(th)), th)
+
+
+def test_algorithms_1_and_2_equal_dense_products():
+    A, L, g = small_graph()
+    n = g.n
+    z = np.random.default_rng(1).choice([-1.0, 1.0], n)
+    DA = dense(*A, n)
+    DL = dense(*L, n)
+    assert np.allclose(G.coo_matvec(g.a_rows, A[1].astype(np.int64), A[2], z), DA @ z, rtol=1e-13, atol=1e-12)
+    assert np.allclose(G.coo_llt_matvec(g.r, g.c, g.Lic, z), DL @ (DL.T @ z), rtol=1e-13, atol=1e-12)
+
+
+def test_hutchinson_average_over_all_probes_is_frobenius_norm():
+    # Eq. 4: E_z ||M z||^2 = ||M||_F^2 for Rademacher z; the average over all
+    # 2^n sign vectors is exact
+    rng = np.random.default_rng(4)
+    n = 7
+    M = rng.standard_normal((n, n))
+    Aspd = M @ M.T + n * np.eye(n)
+    A = dense_to_csr(Aspd)
+    Lp = dense_to_csr(np.tril(rng.standard_normal((n, n))) + 3 * np.eye(n))
+    g = G.Graph(A, Lp)
+    DL = dense(*Lp, n)
+    acc = 0.0
+    for signs in itertools.product([-1.0, 1.0], repeat=n):
+        z = np.array(signs)
+        d = G.coo_llt_matvec(g.r, g.c, g.Lic, z) - G.coo_matvec(g.a_rows, A[1].astype(np.int64), A[2], z)
+        acc += d @ d
+    fro = np.linalg.norm(DL @ DL.T - Aspd, "fro") ** 2
+    assert acc / 2 ** n == pytest.approx(fro, rel=1e-12)
+
+
+def test_node_features_brute_force():
+    A, L, g = small_graph(E=2, sigma=1.5, seed=9)
+    n = g.n
+    x = G.node_features(g)
+    B = pattern(A[0], A[1], n)
+    D = dense(*A, n)
+    off = B & ~np.eye(n, dtype=bool)
+    deg = off.sum(1).astype(float)
+    assert np.array_equal(x[:, 0], deg)
+    for i in range(n):
+        nd = deg[off[i]]
+        assert x[i, 1] == nd.max() and x[i, 2] == nd.min()
+        assert x[i, 3] == pytest.approx(nd.mean(), rel=1e-14)
+        assert x[i, 4] == pytest.approx(((nd - nd.mean()) ** 2).mean(), rel=1e-12, abs=1e-12)
+    ad = np.abs(D)
+    assert np.allclose(x[:, 5], np.diag(ad) / ad.sum(1), rtol=1e-14)
+    assert np.allclose(x[:, 6], np.where(off, ad, 0).max(1) / np.diag(ad), rtol=1e-14)
+    ang = np.pi * np.arange(n) / n
+    assert np.allclose(x[:, 7:], np.stack([np.sin(ang), np.cos(ang)], 1), rtol=0, atol=1e-15)
+    # a 3-DOF node's rows of the Q1 matrix share one neighbourhood
+    assert x[0, 0] == x[1, 0] == x[2, 0]
+
+
+def test_zero_output_reproduces_ic():
+    A, L, g = small_graph()
+    th = G.init_params(7, zero_output=True)
+    Lp = G.predict(g, th)
+    assert np.array_equal(Lp, g.Lic)
+
+
+def test_graph_normalization_standardizes():
+    A, L, g = small_graph()
+    th = G.init_params(7)
+    _, C = G.forward(g, th, keep=True)
+    h0, x = C["hs"][0], C["x"]
+    assert np.allclose(h0.mean(0), 0.0, atol=1e-12)
+    vx = x.var(0)
+    assert np.allclose(h0.var(0), vx / (vx + G.GN_EPS), rtol=1e-12)
+
+
+def test_message_passing_selectors():
+    # weights that pick single features give closed forms: they fix which end of
+    # an edge is the row and how the aggregation sums (undirected, diagonal once)
+    A, L, g = small_graph(E=2, sigma=1.2, seed=3)
+    n = g.n
+    d = {name: np.zeros(shape) for name, shape in G.param_layout()}
+    d["gn_gamma"][:] = 1.0  # alpha = beta = 0: h0 = x / sqrt(mean(x^2) + eps)
+    f_r, f_c = 5, 6
+    d["e0_W1"][0, 1 + f_r] = 1.0       # hidden 0 <- h_row[f_r]
+    d["e0_W1"][1, 1 + 9 + f_c] = 1.0   # hidden 1 <- h_col[f_c]
+    d["e0_w2"][0], d["e0_w2"][1] = 1.0, -2.0
+    d["n0_W1"][0, 9] = 0.25            # node hidden 0 <- sum
+    d["n0_W1"][1, 10] = 1.0            # node hidden 1 <- mean
+    d["n0_W2"][3, 0] = 1.0
+    d["n0_W2"][4, 1] = 1.0
+    th = G.pack(d)
+    _, C = G.forward(g, th, keep=True)
+    x = C["x"]
+    h0 = x / np.sqrt((x * x).mean(0) + G.GN_EPS)
+    e = np.tanh(h0[g.r, f_r]) - 2.0 * np.tanh(h0[g.c, f_c])
+    assert np.allclose(C["es"][0], e, rtol=1e-14, atol=1e-15)
+    S = np.zeros((n, n))
+    S[g.r, g.c] = e
+    S = S + np.tril(S, -1).T          # symmetric, diagonal once
+    s = S.sum(1)
+    PL = pattern(L[0], L[1], n)
+    cnt = PL.sum(1) + PL.sum(0) - 1
+    h1 = C["hs"][1]
+    assert np.allclose(h1[:, 3], np.tanh(0.25 * s), rtol=1e-13, atol=1e-15)
+    assert np.allclose(h1[:, 4], np.tanh(s / cnt), rtol=1e-13, atol=1e-15)
+    assert np.allclose(np.delete(h1, [3, 4], 1), 0.0)
+
+
+def test_gradient_matches_central_differences():
+    A, L, g = small_graph(E=2, sigma=1.0, seed=8)
+    th = G.init_params(11, zero_output=False)
+    # alpha away from 1: some features of this small graph are constant, and
+    # alpha = 1 would centre them to zero, where the loss is too curved for
+    # central differences
+    d = G.unpack(th)
+    rng = np.random.default_rng(12)
+    d["gn_alpha"][:] = rng.uniform(0.3, 0.7, 9)
+    d["gn_gamma"][:] = rng.uniform(0.5, 1.5, 9)
+    d["gn_beta"][:] = rng.uniform(-0.2, 0.2, 9)
+    z = np.random.default_rng(2).choice([-1.0, 1.0], g.n)
+    x = G.node_features(g)
+    f, grad = G.loss_and_grad(g, th, z, x)
+    assert f == pytest.approx(G.loss(g, G.predict(g, th, x), z), rel=1e-13)
+    h = 1e-6
+    fd = np.empty_like(th)
+    for k in range(th.size):
+        tp = th.copy(); tp[k] += h
+        tm = th.copy(); tm[k] -= h
+        fd[k] = (G.loss(g, G.predict(g, tp, x), z) - G.loss(g, G.predict(g, tm, x), z)) / (2 * h)
+    scale = np.abs(grad).max()
+    err = np.abs(fd - grad)
+    print(f"loss {f:.6e}, max |grad| {scale:.3e}, max |fd - grad| {err.max():.3e}")
+    assert np.all(err <= 1e-6 * np.abs(grad) + 1e-7 * scale)
+    # every parameter group receives gradient
+    for name, shp in G.param_layout():
+        assert np.abs(G.unpack(grad)[name]).max() > 0, name
+
+
+def test_adam_closed_form_first_step():
+    # the first bias-corrected step moves every parameter by lr * sign(grad)
+    th = np.array([1.0, -2.0, 0.5])
+    gr = np.array([3.0, -0.25, 1e-3])
+    t1, m, v = G.adam_step(th, gr, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=0.0)
+    assert np.allclose(t1, th - 0.01 * np.sign(gr), rtol=1e-15)
