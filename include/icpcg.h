@@ -74,6 +74,7 @@ typedef struct {
 
 typedef struct icpcg_ctx icpcg_ctx;    /* stream, workspace, device properties */
 typedef struct icpcg_mat icpcg_mat;    /* A with its row-group analysis */
+typedef struct icpcg_gnn icpcg_gnn;    /* A prepared for the learned factor correction */
 typedef struct icpcg_prec icpcg_prec;  /* L, L^T, schedules, reduced-precision copies */
 
 /* ---------------------------------------------------------------- context */
@@ -276,6 +277,65 @@ icpcg_status icpcg_autotune(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec
 icpcg_status icpcg_solve_mat(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec *P,
                              const double *B, double *X, int64_t nrhs,
                              const icpcg_solve_opts *opts, icpcg_col_info *info);
+
+/* ------------------------------------------- learned factor correction */
+
+/* The correction of Eq. 2, L_pred = L_IC + GNN(A), with the network of the
+ * Model Architecture section: node features of supplementary Table 2
+ * (degree; max, min, mean and variance of the neighbours' degrees; diagonal
+ * dominance |a_ii| / sum_j |a_ij|; diagonal decay max_{j != i} |a_ij| / |a_ii|;
+ * sin and cos of pi i / n), edge input a_ij / s with s the population
+ * standard deviation of tril(A)'s entries, graph normalization of the node
+ * features, and three message-passing blocks (supplementary Eqs. 7-9): an
+ * edge updater (two layers, hidden 8, tanh) on [e, x_row, x_col], sum and
+ * mean aggregation over the edges at a node (an edge counts at both of its
+ * nodes, the diagonal once), a node updater (two layers, hidden 8, tanh) on
+ * [x, sum, mean]; blocks 2 and 3 take [e_input, e_previous] as edge input.
+ * The last block's edge value g gives L = L_IC + sqrt(s) g off the diagonal
+ * and L = L_IC exp(g / 2) on it. Everything is FP64.
+ *
+ * Parameters are one FP64 device vector of icpcg_gnn_num_params() values in
+ * this order: normalization alpha[9], gamma[9], beta[9]; then edge block 1,
+ * node block 1, edge block 2, node block 2, edge block 3, where an edge block
+ * is W1[8][d] (row-major, d = 19 in block 1, 20 after), b1[8], w2[8], b2[1]
+ * and a node block is W1[8][11], b1[8], W2[9][8], b2[9]. */
+int64_t icpcg_gnn_num_params(void);
+
+/* Prepare A (full symmetric CSR, FP64, device) for the network, with the
+ * pattern of P's factor, which must be exactly tril(A)'s. P must be an FP64
+ * preconditioner holding L_IC; its values are copied (later updates of P do
+ * not change L_IC here) but its pattern arrays are used in place: P, and A's
+ * buffers, must outlive G. The handle keeps the activations of its last pass:
+ * calls on one handle must not overlap. Errors: ICPCG_E_INVALID (pattern
+ * mismatch, P not FP64, tril(A) with zero spread), ICPCG_E_NOMEM. */
+icpcg_status icpcg_gnn_create(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P,
+                              icpcg_gnn **G);
+icpcg_status icpcg_gnn_destroy(icpcg_gnn *G);
+
+/* The network's inputs (device): node features x[n][9] (nullable), edge
+ * inputs e[nnz] in the factor's CSR order (nullable); *scale (host, nullable)
+ * receives s. */
+icpcg_status icpcg_gnn_inputs(icpcg_ctx *ctx, const icpcg_gnn *G, double *x, double *e,
+                              double *scale);
+
+/* L_pred values (device, FP64, the factor's CSR order) for parameters theta
+ * (device). Stream-ordered. */
+icpcg_status icpcg_gnn_forward(icpcg_ctx *ctx, icpcg_gnn *G, const double *theta, double *L_val);
+
+/* Loss of Eq. 5 with one probe z (device, n values, normally +-1, drawn by
+ * the caller): ||L L^T z - A z||^2 / ||A z||^2 with L = L_pred(theta), and
+ * its gradient with respect to theta. loss (device, 1 value) and grad
+ * (device, num_params values) are overwritten, or added to when accumulate
+ * is nonzero (to sum over a batch of matrices). Stream-ordered. */
+icpcg_status icpcg_gnn_loss_grad(icpcg_ctx *ctx, icpcg_gnn *G, const double *theta,
+                                 const double *z, double *loss, double *grad, int accumulate);
+
+/* One Adam step on count FP64 device values: m and v (device) are the
+ * moment estimates, t >= 1 the step number (bias corrections 1 - beta^t).
+ * theta -= lr * m_hat / (sqrt(v_hat) + eps). Stream-ordered. */
+icpcg_status icpcg_adam_step(icpcg_ctx *ctx, double *theta, const double *grad, double *m, double *v,
+                             int64_t count, int64_t t, double lr, double beta1, double beta2,
+                             double eps);
 
 /* Synchronize the context's stream and report a device-side failure of the
  * non-synchronizing calls (a dependency wait that hit its time limit). */

@@ -95,6 +95,13 @@ def load():
         "icpcg_mat_spmv": ([P, P, P, P, i64], st),
         "icpcg_solve_mat": ([P, P, P, P, P, i64, C.POINTER(SolveOpts), C.POINTER(ColInfo)], st),
         "icpcg_autotune": ([P, P, P, i64, C.POINTER(TuneInfo)], st),
+        "icpcg_gnn_num_params": ([], i64),
+        "icpcg_gnn_create": ([P, C.POINTER(Csr), P, C.POINTER(P)], st),
+        "icpcg_gnn_destroy": ([P], st),
+        "icpcg_gnn_inputs": ([P, P, P, P, C.POINTER(C.c_double)], st),
+        "icpcg_gnn_forward": ([P, P, P, P], st),
+        "icpcg_gnn_loss_grad": ([P, P, P, P, P, P, st], st),
+        "icpcg_adam_step": ([P, P, P, P, P, i64, i64, C.c_double, C.c_double, C.c_double, C.c_double], st),
         "icpcg_version": ([], C.c_char_p),
     }
     for name, (args, res) in sig.items():

@@ -812,3 +812,54 @@ extern "C" icpcg_status icpcg_solve(icpcg_ctx *ctx, const icpcg_csr *A, const ic
   if (st) return finish(ctx, st);
   return solve_impl(ctx, &M, P, B, X, nrhs, opts, info);
 }
+
+// ------------------------------------------------- learned factor correction
+
+extern "C" int64_t icpcg_gnn_num_params(void) { return gnn_num_params(); }
+
+extern "C" icpcg_status icpcg_gnn_create(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, icpcg_gnn **out) {
+  if (!ctx || !valid_csr_args(A) || !P || !out || A->n != P->n || A->n == 0)
+    return fail(ctx, ICPCG_E_INVALID, "gnn_create: bad arguments");
+  *out = nullptr;
+  if (P->dtype != ICPCG_F64) return fail(ctx, ICPCG_E_INVALID, "gnn_create: the preconditioner must be FP64 (L_IC)");
+  int st = check_matrix(ctx, A, 0);
+  if (st) return finish(ctx, st);
+  icpcg_gnn *G = new (std::nothrow) icpcg_gnn();
+  if (!G) return finish(ctx, ICPCG_E_NOMEM);
+  if ((st = gnn_setup(G, A, P, ctx->stream))) {
+    delete G;
+    return finish(ctx, st);
+  }
+  *out = G;
+  return ICPCG_OK;
+}
+
+extern "C" icpcg_status icpcg_gnn_destroy(icpcg_gnn *G) {
+  delete G;
+  return ICPCG_OK;
+}
+
+extern "C" icpcg_status icpcg_gnn_inputs(icpcg_ctx *ctx, const icpcg_gnn *G, double *x, double *e, double *scale) {
+  if (!ctx || !G) return fail(ctx, ICPCG_E_INVALID, "gnn_inputs: bad arguments");
+  if (scale) *scale = G->scale;
+  return finish(ctx, gnn_inputs(G, x, e, ctx->stream));
+}
+
+extern "C" icpcg_status icpcg_gnn_forward(icpcg_ctx *ctx, icpcg_gnn *G, const double *theta, double *L_val) {
+  if (!ctx || !G || !theta || !L_val) return fail(ctx, ICPCG_E_INVALID, "gnn_forward: bad arguments");
+  return finish(ctx, gnn_forward(G, theta, L_val, false, ctx->stream));
+}
+
+extern "C" icpcg_status icpcg_gnn_loss_grad(icpcg_ctx *ctx, icpcg_gnn *G, const double *theta, const double *z,
+                                            double *loss, double *grad, int accumulate) {
+  if (!ctx || !G || !theta || !z || !loss || !grad) return fail(ctx, ICPCG_E_INVALID, "gnn_loss_grad: bad arguments");
+  return finish(ctx, gnn_loss_grad(G, theta, z, loss, grad, accumulate != 0, ctx->stream));
+}
+
+extern "C" icpcg_status icpcg_adam_step(icpcg_ctx *ctx, double *theta, const double *grad, double *m, double *v,
+                                        int64_t count, int64_t t, double lr, double beta1, double beta2, double eps) {
+  if (!ctx || count < 0 || t < 1 || (count > 0 && (!theta || !grad || !m || !v)))
+    return fail(ctx, ICPCG_E_INVALID, "adam_step: bad arguments");
+  if (count == 0) return ICPCG_OK;
+  return finish(ctx, adam_step(theta, grad, m, v, count, t, lr, beta1, beta2, eps, ctx->stream));
+}

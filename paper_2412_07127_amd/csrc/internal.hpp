@@ -138,6 +138,20 @@ struct icpcg_prec {
   int64_t nlev_rows_L = -1, nlev_rows_U = -1;  // row level counts (on demand)
 };
 
+// A matrix prepared for the learned correction: pattern and transpose map of
+// the preconditioner it was made from (which must outlive it), a copy of
+// L_IC, node features, edge inputs and their scale, and the activations and
+// gradients of the last pass.
+struct icpcg_gnn {
+  int64_t n = 0, nnz = 0;
+  icpcg_csr A{};
+  const icpcg_prec *P = nullptr;
+  icpcg::DevBuf erow, aedge, lic, deg, x, e0, red, flag, tmp, part, pp;
+  double scale = 0.0;
+  icpcg::DevBuf d, mu, sd, h[3], e[3], q[3], nin[2], Q[2], L;
+  icpcg::DevBuf az, u, llz, r, ltr, sq2, sums, dout, de, deprev, dhr, dhc, dp, dh, direct, ds, dP, rows3, dd;
+};
+
 namespace icpcg {
 
 // ------------------------------------------------------------ primitives
@@ -187,6 +201,16 @@ int ic0_factor_levels(const int64_t *lrp, const int32_t *lci, double *lv, const 
                       int64_t n, const int32_t *perm, const std::vector<int32_t> &level_ptr,
                       double alpha, int *fail_flag, double *pivots, hipStream_t s, int max_row_len);
 int ic0_max_row();
+
+// learned correction of the factor (gnn.hip)
+int gnn_num_params();
+int gnn_setup(icpcg_gnn *G, const icpcg_csr *A, const icpcg_prec *P, hipStream_t s);
+int gnn_inputs(const icpcg_gnn *G, double *x, double *e, hipStream_t s);
+int gnn_forward(icpcg_gnn *G, const double *theta, double *L_out, bool keep, hipStream_t s);
+int gnn_loss_grad(icpcg_gnn *G, const double *theta, const double *z, double *loss, double *grad, bool accumulate,
+                  hipStream_t s);
+int adam_step(double *th, const double *g, double *m, double *v, int64_t count, int64_t t, double lr, double b1,
+              double b2, double eps, hipStream_t s);
 int spmv_default_slots(int R);
 
 // partials/cols non-null: fused p^T w reduction and alpha update (active must
