@@ -49,6 +49,7 @@ def _load():
     lib.orc_round_bf16.restype = C.c_float
     lib.orc_cast_values.argtypes = [i64, P, C.c_int, P]
     lib.orc_apply_f32.argtypes = [i64, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_pcg_simple.argtypes = [i64, P, P, P, C.c_int, P, P, C.c_double, i64, C.c_int, P, P, P, P, P]
     lib.orc_pcg.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, C.c_double, i64, C.c_int,
                             C.c_int, P, P, P, P, P]
     lib.orc_apply.argtypes = [i64, P, P, P, P, P, P, P, P, P]
@@ -233,6 +234,30 @@ def pcg(A, L, U, b, x0=None, rtol=1e-8, max_iter=None, max_replace=3, prec=0, hi
     st = _load().orc_pcg(n, _p(rp), _p(ci), _p(v), _p(lrp), _p(lci), _p(lv), _p(urp), _p(uci),
                          _p(uv), _p(b), _p(x), rtol, max_iter, max_replace, prec, C.byref(it),
                          C.byref(rep), C.byref(rr), C.byref(tr), _p(hist))
+    out = dict(x=x, status=st, iters=it.value, replacements=rep.value, relres=rr.value,
+               true_relres=tr.value)
+    if history:
+        out["hist"] = hist[:it.value + 1]
+    return out
+
+
+def pcg_simple(A, b, kind, x0=None, rtol=1e-8, max_iter=None, max_replace=3, history=False):
+    """The PCG of `pcg` with Table 1's baselines: kind "jacobi" (z_i = r_i / a_ii)
+    or "none" (plain CG). Same result dict."""
+    k = {"jacobi": 1, "none": 2}[kind]
+    rp, ci, v = _csr(*A)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    if max_iter is None:
+        max_iter = default_max_iter(n)
+    it = C.c_int64(0)
+    rep = C.c_int(0)
+    rr = C.c_double(0)
+    tr = C.c_double(0)
+    hist = np.zeros(max_iter + 1) if history else None
+    st = _load().orc_pcg_simple(n, _p(rp), _p(ci), _p(v), k, _p(b), _p(x), rtol, max_iter, max_replace,
+                                C.byref(it), C.byref(rep), C.byref(rr), C.byref(tr), _p(hist))
     out = dict(x=x, status=st, iters=it.value, replacements=rep.value, relres=rr.value,
                true_relres=tr.value)
     if history:

@@ -335,10 +335,17 @@ typedef struct {
   const float *lv32, *uv32; /* non-null: apply the factor in float */
   double *y;
   float *y32, *z32;
+  int kind;                  /* 0: L L^T; 1: Jacobi (diag); 2: none */
+  const double *diag;        /* kind 1: a_ii */
 } orc_prec;
 
 static void prec_apply(const orc_prec *P, const double *r, double *z) {
-  if (P->lv32) {
+  if (P->kind == 1) {
+    /* Jacobi: the reciprocal of A's diagonal as the inverse (Baseline Methods) */
+    for (int64_t i = 0; i < P->n; ++i) z[i] = r[i] / P->diag[i];
+  } else if (P->kind == 2) {
+    for (int64_t i = 0; i < P->n; ++i) z[i] = r[i];
+  } else if (P->lv32) {
     orc_apply_f32(P->n, P->lrp, P->lci, P->lv32, P->urp, P->uci, P->uv32, r, z, P->y32, P->z32);
   } else {
     orc_trsv_lower(P->n, P->lrp, P->lci, P->lv, r, P->y);
@@ -499,4 +506,31 @@ void orc_apply_adjoint(int64_t n, const int64_t *lrp, const int32_t *lci, const 
       dL[q] = -s;
     }
   free(c0); free(c1); free(c2);
+}
+
+/* The same PCG with the two baselines of Table 1: kind 1 = Jacobi (z_i =
+ * r_i / a_ii), kind 2 = no preconditioner (z = r, plain CG). A must store
+ * its diagonal. */
+int orc_pcg_simple(int64_t n, const int64_t *rp, const int32_t *ci, const double *v, int kind,
+                   const double *b, double *x, double rtol, int64_t max_iter, int max_replace,
+                   int64_t *iters_out, int *repl_out, double *relres_out, double *true_relres_out,
+                   double *hist) {
+  orc_prec P;
+  memset(&P, 0, sizeof(P));
+  P.n = n;
+  P.kind = kind;
+  double *d = NULL;
+  if (kind == 1) {
+    d = (double *)malloc((size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+      d[i] = 0.0;
+      for (int64_t q = rp[i]; q < rp[i + 1]; ++q)
+        if (ci[q] == i) d[i] = v[q];
+    }
+    P.diag = d;
+  }
+  int st = orc_pcg_run(&P, n, rp, ci, v, b, x, rtol, max_iter, max_replace, iters_out,
+                       repl_out, relres_out, true_relres_out, hist);
+  free(d);
+  return st;
 }

@@ -459,3 +459,49 @@ def test_dot_is_nearly_exactly_rounded():
     got = oracle.dot(a, b)
     assert abs(got - exact) <= 4 * np.finfo(float).eps * math.fsum(np.abs(a * b))
     assert oracle.dot(np.ones(10), np.arange(10.0)) == 45.0
+
+
+# ------------------------------------------- Table 1 baselines (None, Jacobi)
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_plain_cg_k_distinct_eigenvalues(k):
+    """Unpreconditioned CG: k distinct eigenvalues -> k products."""
+    n = 40
+    M = spectrum_spd(n, np.linspace(2.0, 7.0, k), seed=10 + k)
+    A = csr_of(M, np.ones((n, n), bool))
+    b = np.random.default_rng(k).standard_normal(n)
+    res = oracle.pcg_simple(A, b, "none", rtol=1e-10, max_replace=0)
+    assert res["status"] == oracle.OK and res["iters"] == k
+    assert np.allclose(res["x"], np.linalg.solve(M, b), rtol=1e-8)
+
+
+def test_jacobi_equals_cg_on_symmetrically_scaled_matrix():
+    """Jacobi-PCG on A is CG on D^-1/2 A D^-1/2 with x = D^-1/2 x_hat, b_hat =
+    D^-1/2 b: the same iterates at every k."""
+    p = q1_elasticity(3, 2.0, 17)
+    M = p.to_scipy().toarray()
+    d = np.diag(M).copy()
+    s = 1.0 / np.sqrt(d)
+    Ms = M * s[:, None] * s[None, :]
+    pat = M != 0
+    A = csr_of(M, pat)
+    As = csr_of(Ms, pat)
+    b = np.random.default_rng(3).standard_normal(p.n)
+    for k in (1, 4, 15):
+        rj = oracle.pcg_simple(A, b, "jacobi", rtol=0.0, max_iter=k, max_replace=0)
+        rn = oracle.pcg_simple(As, s * b, "none", rtol=0.0, max_iter=k, max_replace=0)
+        assert rj["iters"] == rn["iters"] == k
+        assert np.linalg.norm(rj["x"] - s * rn["x"]) <= 1e-10 * np.linalg.norm(rj["x"])
+    full = oracle.pcg_simple(A, b, "jacobi", rtol=1e-10)
+    assert full["status"] == oracle.OK
+    assert np.allclose(full["x"], np.linalg.solve(M, b), rtol=1e-7, atol=1e-9 * np.abs(full["x"]).max())
+
+
+def test_jacobi_on_diagonal_matrix_one_iteration():
+    n = 30
+    D = np.diag(np.random.default_rng(1).uniform(1, 100, n))
+    A = csr_of(D, np.eye(n, dtype=bool))
+    b = np.random.default_rng(2).standard_normal(n)
+    res = oracle.pcg_simple(A, b, "jacobi", rtol=1e-12)
+    assert res["iters"] == 1
+    assert np.allclose(res["x"], b / np.diag(D), rtol=1e-14)
