@@ -129,6 +129,20 @@ icpcg_status icpcg_factor(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *L_row_ptr
  * non-positive diagonal, non-finite value). */
 icpcg_status icpcg_prec_create(icpcg_ctx *ctx, const icpcg_csr *L, icpcg_dtype apply_dtype,
                                icpcg_prec **P);
+
+typedef enum {
+  ICPCG_PREC_FACTOR = 0,  /* P = L L^T (icpcg_prec_create) */
+  ICPCG_PREC_JACOBI = 1,  /* P = diag(A): z_i = r_i / a_ii (Baseline Methods, Table 1) */
+  ICPCG_PREC_NONE = 2     /* P = I: plain CG (Table 1) */
+} icpcg_prec_kind;
+
+/* The baselines of Table 1 as preconditioners for icpcg_solve: Jacobi keeps
+ * a copy of A's diagonal (which must be stored and positive); none keeps only
+ * n. They apply in FP64; calls that need a triangular factor (trsv, apply,
+ * apply_backward, levels, transpose, update_values, gnn_create) reject them
+ * with ICPCG_E_INVALID. */
+icpcg_status icpcg_prec_create_simple(icpcg_ctx *ctx, const icpcg_csr *A, icpcg_prec_kind kind,
+                                      icpcg_prec **P);
 icpcg_status icpcg_prec_destroy(icpcg_prec *P);
 
 /* Replace the factor's values (same pattern, FP64, CSR order of L) and
@@ -144,6 +158,7 @@ typedef struct {
   int64_t nsn_levels_L;    /* dependent steps of the forward schedule */
   int64_t nsn_levels_U;    /* dependent steps of the backward schedule */
   int dtype;               /* icpcg_dtype of application */
+  int kind;                /* icpcg_prec_kind (0 for a factor; other kinds report n only) */
 } icpcg_prec_info;
 
 icpcg_status icpcg_prec_get_info(icpcg_ctx *ctx, const icpcg_prec *P, icpcg_prec_info *info);

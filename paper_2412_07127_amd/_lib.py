@@ -18,6 +18,7 @@ OK, E_INVALID, E_PIVOT, E_BREAKDOWN, E_MAXITER, E_NONFINITE, E_DEVICE, E_NOMEM, 
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_PIVOT", 3: "E_BREAKDOWN", 4: "E_MAXITER",
                 5: "E_NONFINITE", 6: "E_DEVICE", 7: "E_NOMEM", 8: "E_TRUE_RESIDUAL"}
 F64, F32, BF16 = 0, 1, 2
+PREC_FACTOR, PREC_JACOBI, PREC_NONE = 0, 1, 2
 
 
 class Csr(C.Structure):
@@ -38,7 +39,7 @@ class PrecInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("nlevels_L", C.c_int64),
                 ("nlevels_U", C.c_int64), ("nsupernodes_L", C.c_int64),
                 ("nsupernodes_U", C.c_int64), ("nsn_levels_L", C.c_int64),
-                ("nsn_levels_U", C.c_int64), ("dtype", C.c_int)]
+                ("nsn_levels_U", C.c_int64), ("dtype", C.c_int), ("kind", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -80,6 +81,7 @@ def load():
         "icpcg_factor": ([P, C.POINTER(Csr), P, P, P, C.POINTER(FactorOpts), C.POINTER(FactorInfo)], st),
         "icpcg_prec_create": ([P, C.POINTER(Csr), st, C.POINTER(P)], st),
         "icpcg_prec_destroy": ([P], st),
+        "icpcg_prec_create_simple": ([P, C.POINTER(Csr), st, C.POINTER(P)], st),
         "icpcg_prec_update_values": ([P, P, P], st),
         "icpcg_prec_get_info": ([P, P, C.POINTER(PrecInfo)], st),
         "icpcg_prec_levels": ([P, P, P, P, P, P, P, P], st),

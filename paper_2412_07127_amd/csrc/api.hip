@@ -21,6 +21,15 @@ __global__ void k_row_len(const int64_t *rp, int64_t n, int32_t *len) {
     len[i] = (int32_t)(rp[i + 1] - rp[i]);
 }
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+// d_i = a_ii (0 when row i stores no diagonal)
+__global__ void k_extract_diag(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, double *d) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double x = 0.0;
+    for (int64_t t = rp[i]; t < rp[i + 1]; ++t)
+      if (ci[t] == i) x = v[t];
+    d[i] = x;
+  }
+}
 }  // namespace
 
 void set_error(const std::string &msg) { g_err = msg; }
@@ -46,6 +55,16 @@ icpcg_status fail(icpcg_ctx *ctx, icpcg_status st, const std::string &msg) {
 
 bool valid_csr_args(const icpcg_csr *A) {
   return A && A->n >= 0 && A->nnz >= 0 && A->n < INT32_MAX && (A->n == 0 || (A->row_ptr && A->col && A->val));
+}
+
+// Calls that need the triangular factor reject the baseline kinds.
+bool not_factor(icpcg_ctx *ctx, const icpcg_prec *P, const char *what) {
+  if (P && P->kind != ICPCG_PREC_FACTOR) {
+    set_error(std::string(what) + ": the preconditioner has no triangular factor (Jacobi or none)");
+    finish(ctx, ICPCG_E_INVALID);
+    return true;
+  }
+  return false;
 }
 
 bool pow2_width(int64_t r) { return r == 1 || r == 2 || r == 4 || r == 8 || r == 16; }
@@ -296,6 +315,37 @@ icpcg_status icpcg_prec_create(icpcg_ctx *ctx, const icpcg_csr *L, icpcg_dtype d
   return ICPCG_OK;
 }
 
+icpcg_status icpcg_prec_create_simple(icpcg_ctx *ctx, const icpcg_csr *A, icpcg_prec_kind kind, icpcg_prec **out) {
+  if (!ctx || !valid_csr_args(A) || !out || (kind != ICPCG_PREC_JACOBI && kind != ICPCG_PREC_NONE))
+    return fail(ctx, ICPCG_E_INVALID, "prec_create_simple: bad arguments");
+  *out = nullptr;
+  icpcg_prec *P = new (std::nothrow) icpcg_prec();
+  if (!P) return finish(ctx, ICPCG_E_NOMEM);
+  P->n = A->n;
+  P->kind = kind;
+  if (kind == ICPCG_PREC_JACOBI && A->n > 0) {
+    int st = check_matrix(ctx, A, 0);
+    if (!st && P->diag.reserve(A->n * 8)) st = ICPCG_E_NOMEM;
+    if (st) {
+      delete P;
+      return finish(ctx, st);
+    }
+    hipLaunchKernelGGL(k_extract_diag, dim3(1024), dim3(256), 0, ctx->stream, A->row_ptr, A->col,
+                       (const double *)A->val, A->n, P->diag.as<double>());
+    double dmin = 0.0;
+    if (hipGetLastError() != hipSuccess || reduce_min_f64(P->diag.as<double>(), A->n, ctx->stream, &dmin) != ICPCG_OK) {
+      delete P;
+      return fail(ctx, ICPCG_E_DEVICE, "prec_create_simple: diagonal extraction failed");
+    }
+    if (!(dmin > 0.0)) {
+      delete P;
+      return fail(ctx, ICPCG_E_INVALID, "prec_create_simple: Jacobi needs a positive diagonal");
+    }
+  }
+  *out = P;
+  return ICPCG_OK;
+}
+
 icpcg_status icpcg_prec_destroy(icpcg_prec *P) {
   delete P;
   return ICPCG_OK;
@@ -303,6 +353,7 @@ icpcg_status icpcg_prec_destroy(icpcg_prec *P) {
 
 icpcg_status icpcg_prec_update_values(icpcg_ctx *ctx, icpcg_prec *P, const double *L_val) {
   if (!ctx || !P || !L_val) return fail(ctx, ICPCG_E_INVALID, "prec_update_values: bad arguments");
+  if (not_factor(ctx, P, "prec_update_values")) return ICPCG_E_INVALID;
   icpcg_csr L{P->n, P->nnz, P->lrp.as<int64_t>(), P->lci.as<int32_t>(), L_val};
   int st = check_matrix(ctx, &L, 1);
   if (st) return finish(ctx, st);
@@ -314,6 +365,13 @@ icpcg_status icpcg_prec_update_values(icpcg_ctx *ctx, icpcg_prec *P, const doubl
 icpcg_status icpcg_prec_get_info(icpcg_ctx *ctx, const icpcg_prec *Pc, icpcg_prec_info *info) {
   if (!ctx || !Pc || !info) return fail(ctx, ICPCG_E_INVALID, "prec_get_info: bad arguments");
   icpcg_prec *P = const_cast<icpcg_prec *>(Pc);
+  if (P->kind != ICPCG_PREC_FACTOR) {
+    *info = icpcg_prec_info{};
+    info->n = P->n;
+    info->dtype = ICPCG_F64;
+    info->kind = P->kind;
+    return ICPCG_OK;
+  }
   int st;
   if (P->nlev_rows_L < 0) {
     if ((st = row_levels(P->lrp.as<int64_t>(), P->lci.as<int32_t>(), P->n, false, nullptr, nullptr, nullptr,
@@ -334,12 +392,14 @@ icpcg_status icpcg_prec_get_info(icpcg_ctx *ctx, const icpcg_prec *Pc, icpcg_pre
   info->nsn_levels_L = P->sl.nlev;
   info->nsn_levels_U = P->su.nlev;
   info->dtype = (int)P->dtype;
+  info->kind = P->kind;
   return ICPCG_OK;
 }
 
 icpcg_status icpcg_prec_levels(icpcg_ctx *ctx, const icpcg_prec *Pc, int32_t *level_L, int32_t *perm_L,
                                int32_t *level_ptr_L, int32_t *level_U, int32_t *perm_U, int32_t *level_ptr_U) {
   if (!ctx || !Pc) return fail(ctx, ICPCG_E_INVALID, "prec_levels: bad arguments");
+  if (not_factor(ctx, Pc, "prec_levels")) return ICPCG_E_INVALID;
   icpcg_prec *P = const_cast<icpcg_prec *>(Pc);
   int st;
   if (level_L || perm_L || level_ptr_L) {
@@ -359,6 +419,7 @@ icpcg_status icpcg_prec_levels(icpcg_ctx *ctx, const icpcg_prec *Pc, int32_t *le
 
 icpcg_status icpcg_prec_transpose(icpcg_ctx *ctx, const icpcg_prec *P, int64_t *urp, int32_t *uci, double *uval) {
   if (!ctx || !P) return fail(ctx, ICPCG_E_INVALID, "prec_transpose: bad arguments");
+  if (not_factor(ctx, P, "prec_transpose")) return ICPCG_E_INVALID;
   hipStream_t s = ctx->stream;
   if ((urp && hipMemcpyAsync(urp, P->urp.p, (P->n + 1) * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
       (uci && hipMemcpyAsync(uci, P->uci.p, P->nnz * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
@@ -379,6 +440,7 @@ icpcg_status icpcg_trsv(icpcg_ctx *ctx, const icpcg_prec *P, int transpose, cons
                         int64_t nrhs) {
   if (!ctx || !P || !R || !Y || !pow2_width(nrhs))
     return fail(ctx, ICPCG_E_INVALID, "trsv: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
+  if (not_factor(ctx, P, "trsv")) return ICPCG_E_INVALID;
   const bool lo = P->dtype != ICPCG_F64;
   int st = fill_pending(Y, P->n * nrhs, lo, ctx->stream);
   if (st) return finish(ctx, st);
@@ -390,6 +452,7 @@ icpcg_status icpcg_apply(icpcg_ctx *ctx, const icpcg_prec *P, const void *R, int
                          int64_t nrhs) {
   if (!ctx || !P || !R || !Y || !Z || !pow2_width(nrhs))
     return fail(ctx, ICPCG_E_INVALID, "apply: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
+  if (not_factor(ctx, P, "apply")) return ICPCG_E_INVALID;
   const bool lo = P->dtype != ICPCG_F64;
   hipStream_t s = ctx->stream;
   int st;
@@ -404,6 +467,7 @@ icpcg_status icpcg_apply_backward(icpcg_ctx *ctx, const icpcg_prec *P, const voi
                                   void *Ybar, void *dR, void *dL, int64_t nrhs) {
   if (!ctx || !P || !G || !Y || !Z || !Ybar || !dR || !dL || !pow2_width(nrhs))
     return fail(ctx, ICPCG_E_INVALID, "apply_backward: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
+  if (not_factor(ctx, P, "apply_backward")) return ICPCG_E_INVALID;
   const bool lo = P->dtype != ICPCG_F64;
   hipStream_t s = ctx->stream;
   int st;
@@ -456,8 +520,14 @@ int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const
   const int *act = &fl->n_active;
   int st;
   for (int k = 0; k < count; ++k) {
-    if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err, act))) return st;
-    if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err, act))) return st;
+    if (P->kind != ICPCG_PREC_FACTOR) {
+      if ((st = pcg_diag_apply(n, R, b.r, P->kind == ICPCG_PREC_JACOBI ? P->diag.as<double>() : nullptr,
+                               static_cast<double *>(b.z), act, s)))
+        return st;
+    } else {
+      if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err, act))) return st;
+      if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err, act))) return st;
+    }
     if ((st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, b.cols, fl, s))) return st;
     if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.z, b.cols, fl, s))) return st;
     if ((st = spmv_pass(A, b, b.p, b.w, R, s, b.partials, b.cols, act))) return st;
@@ -476,6 +546,7 @@ int step_graph(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const Pa
       u(A->row_ptr), u(A->col), u(A->val), (uintptr_t)A->n, u(b.grec), (uintptr_t)b.ngroups, u(P),
       (uintptr_t)P->dtype, u(P->lci.p), u(P->uci.p), u(P->lval.p), u(P->uval.p), u(P->lval_lo.p),
       u(P->uval_lo.p), u(P->sl.items.p), u(P->su.items.p), (uintptr_t)P->sl.nsn, (uintptr_t)P->su.nsn,
+      (uintptr_t)P->kind, u(P->diag.p),
       u(b.r), u(b.p), u(b.w), u(b.y), u(b.z), u(b.X), u(b.partials), u(b.cols), u(dev_flags(ctx)),
       (uintptr_t)R, (uintptr_t)max_iter, (uintptr_t)count, (uintptr_t)ctx->dev.wait_ticks,
       (uintptr_t)ctx->dev.trsv_waves_per_cu, (uintptr_t)spmv_grouped_default_slots(R),
@@ -611,6 +682,12 @@ int tune_width(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_prec *P, int64_t 
   }
   auto one_step = [&](int w) -> int {
     int r;
+    if (P->kind != ICPCG_PREC_FACTOR) {
+      if ((r = pcg_diag_apply(n, w, ws.r.as<double>(), P->kind == ICPCG_PREC_JACOBI ? P->diag.as<double>() : nullptr,
+                              ws.z.as<double>(), nullptr, s)))
+        return r;
+      return spmv_pass(A, b, ws.p.as<double>(), ws.w.as<double>(), w, s);
+    }
     if ((r = fill_pending(ws.y.p, n * w, lo, s))) return r;
     if ((r = trsv(P, false, ws.r.p, true, ws.y.p, w, w, s, ctx->dev, err))) return r;
     if ((r = fill_pending(ws.z.p, n * w, lo, s))) return r;
@@ -821,6 +898,7 @@ extern "C" icpcg_status icpcg_gnn_create(icpcg_ctx *ctx, const icpcg_csr *A, con
   if (!ctx || !valid_csr_args(A) || !P || !out || A->n != P->n || A->n == 0)
     return fail(ctx, ICPCG_E_INVALID, "gnn_create: bad arguments");
   *out = nullptr;
+  if (not_factor(ctx, P, "gnn_create")) return ICPCG_E_INVALID;
   if (P->dtype != ICPCG_F64) return fail(ctx, ICPCG_E_INVALID, "gnn_create: the preconditioner must be FP64 (L_IC)");
   int st = check_matrix(ctx, A, 0);
   if (st) return finish(ctx, st);

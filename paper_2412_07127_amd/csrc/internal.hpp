@@ -130,6 +130,8 @@ struct icpcg_mat {
 struct icpcg_prec {
   int64_t n = 0, nnz = 0;
   icpcg_dtype dtype = ICPCG_F64;
+  int kind = ICPCG_PREC_FACTOR;      // icpcg_prec_kind
+  icpcg::DevBuf diag;                // f64[n]: A's diagonal (Jacobi)
   icpcg::DevBuf lrp, lci, lval;      // L (int64, int32, f64)
   icpcg::DevBuf urp, uci, uval;      // U = L^T (int64, int32, f64)
   icpcg::DevBuf upos;                // int32: L position of each U entry
@@ -250,6 +252,9 @@ int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const
 int pcg_true_residual(int64_t n, int R, const double *B, double *W, double *partials,
                       ColState *cols, int64_t max_iter, int max_replace, int final_pass,
                       SolveFlags *flags, hipStream_t s);
+// z = r / d (Jacobi, d non-null) or z = r (no preconditioner) for an n x R
+// block; returns at once when *active == 0.
+int pcg_diag_apply(int64_t n, int R, const double *r, const double *d, double *z, const int *active, hipStream_t s);
 int pcg_replace_r(int64_t n, int R, const double *W, double *r, ColState *cols, hipStream_t s);
 int gather_cols(int64_t n, int R, const double *src, int64_t lds, int64_t c0, int nc, double *dst,
                 hipStream_t s);

@@ -292,6 +292,16 @@ __global__ __launch_bounds__(kBlock) void k_replace_r(int64_t n, const double *_
   }
 }
 
+// z = r / d_i (Jacobi: the reciprocal of A's diagonal as the inverse) or z = r
+// (no preconditioner) for an n x R block.
+__global__ __launch_bounds__(kBlock) void k_diag_apply(int64_t n, int R, const double *__restrict__ r,
+                                                       const double *__restrict__ d, double *__restrict__ z,
+                                                       const int *__restrict__ active) {
+  if (active && *active == 0) return;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * R; e += (int64_t)gridDim.x * blockDim.x)
+    z[e] = d ? r[e] / d[e / R] : r[e];
+}
+
 __global__ void k_gather_cols(int64_t n, int R, const double *__restrict__ src, int64_t lds, int64_t c0, int nc,
                               double *__restrict__ dst) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * R; e += (int64_t)gridDim.x * blockDim.x) {
@@ -408,6 +418,12 @@ int pcg_true_residual(int64_t n, int R, const double *B, double *W, double *part
 
 int pcg_replace_r(int64_t n, int R, const double *W, double *r, ColState *cols, hipStream_t s) {
   ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_replace_r<RR>, dim3(vec_grid(n, R)), dim3(kBlock), 0, s, n, W, r, cols));
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int pcg_diag_apply(int64_t n, int R, const double *r, const double *d, double *z, const int *active, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_apply, dim3(vec_grid(n, R)), dim3(kBlock), 0, s, n, R, r, d, z, active);
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
 }

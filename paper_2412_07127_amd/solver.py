@@ -182,6 +182,17 @@ class Context:
         self._check(self.lib.icpcg_prec_create(self.h, C.byref(l), DTYPES[dtype], C.byref(h)))
         return Preconditioner(self, h, Lf, dtype)
 
+    def prec_simple(self, A: CSR, kind: str) -> "Preconditioner":
+        """Table 1's baselines: kind "jacobi" (z_i = r_i / a_ii) or "none" (plain CG)."""
+        self._bind()
+        k = {"jacobi": L.PREC_JACOBI, "none": L.PREC_NONE}[kind]
+        h = C.c_void_p()
+        a = A.cstruct()
+        self._check(self.lib.icpcg_prec_create_simple(self.h, C.byref(a), k, C.byref(h)))
+        P = Preconditioner(self, h, None, "f64")
+        P.kind, P._n = kind, A.n
+        return P
+
     # ------------------------------------------------------------ kernels
     def spmv(self, A: CSR, X: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         self._bind()
@@ -240,6 +251,8 @@ class Preconditioner:
 
     def __init__(self, ctx: Context, h, Lf: CSR, dtype: str):
         self.ctx, self.h, self.L, self.dtype = ctx, h, Lf, dtype
+        self.kind = "factor"
+        self._n = Lf.n if Lf is not None else 0
 
     def close(self):
         if getattr(self, "h", None):
@@ -254,7 +267,7 @@ class Preconditioner:
 
     @property
     def n(self):
-        return self.L.n
+        return self._n
 
     def vec_dtype(self):
         return torch.float64 if self.dtype == "f64" else torch.float32
