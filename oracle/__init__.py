@@ -286,3 +286,16 @@ def apply_adjoint(L, U, R, G):
     _load().orc_apply_adjoint(n, _p(lrp), _p(lci), _p(lv), _p(urp), _p(uci), _p(uv), m, _p(R),
                               _p(G), _p(Y), _p(Z), _p(Yb), _p(Rb), _p(dL))
     return dict(Y=Y, Z=Z, Ybar=Yb, Rbar=Rb, dL=dL)
+
+
+def dropout(L, eps):
+    """Fill-in dropout of Eq. 10 on a lower CSR factor: an off-diagonal entry
+    with |l_ij| <= eps becomes a structural zero (removed); the diagonal is
+    kept. Returns the new CSR triple (row_ptr int64, col int32, val float64)."""
+    rp, ci, v = (np.asarray(a) for a in L)
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    keep = (ci == rows) | (np.abs(v) > eps)
+    new_rp = np.zeros(n + 1, np.int64)
+    np.add.at(new_rp, rows[keep] + 1, 1)
+    return np.cumsum(new_rp), ci[keep].astype(np.int32), v[keep].astype(np.float64)

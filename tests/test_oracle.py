@@ -505,3 +505,31 @@ def test_jacobi_on_diagonal_matrix_one_iteration():
     res = oracle.pcg_simple(A, b, "jacobi", rtol=1e-12)
     assert res["iters"] == 1
     assert np.allclose(res["x"], b / np.diag(D), rtol=1e-14)
+
+
+# ------------------------------------------------ fill-in dropout (Eq. 10)
+
+def test_dropout_worked_example():
+    # rows: [2], [0.0005 3], [-0.02 0.01 4]; eps = 0.01 keeps |l| > 0.01 and the diagonal
+    L = (np.array([0, 1, 3, 6]), np.array([0, 0, 1, 0, 1, 2], np.int32),
+         np.array([2.0, 0.0005, 3.0, -0.02, 0.01, 4.0]))
+    rp, ci, v = oracle.dropout(L, 0.01)
+    assert rp.tolist() == [0, 1, 2, 4]
+    assert ci.tolist() == [0, 1, 0, 2]
+    assert v.tolist() == [2.0, 3.0, -0.02, 4.0]
+    # eps = 0 removes exact zeros only; a tiny diagonal is never removed
+    L0 = (np.array([0, 1, 3]), np.array([0, 0, 1], np.int32), np.array([1e-30, 0.0, 1.0]))
+    rp, ci, v = oracle.dropout(L0, 0.0)
+    assert rp.tolist() == [0, 1, 2] and ci.tolist() == [0, 1] and v.tolist() == [1e-30, 1.0]
+
+
+def test_dropout_of_ic_factor_is_a_subpattern():
+    p = q1_elasticity(3, 1.5, 21)
+    st, L, *_ = oracle.ic0_shifted(p.row_ptr, p.col, p.val)
+    n = p.n
+    for eps in (0.0, 1e-3, 1e-2, 5e-2):
+        D = lower_dense(*oracle.dropout(L, eps), n)
+        F = lower_dense(*L, n)
+        off = ~np.eye(n, dtype=bool)
+        assert np.array_equal(np.diag(D), np.diag(F))
+        assert np.array_equal(D[off], np.where(np.abs(F) > eps, F, 0.0)[off])
