@@ -145,6 +145,17 @@ icpcg_status icpcg_prec_create_simple(icpcg_ctx *ctx, const icpcg_csr *A, icpcg_
                                       icpcg_prec **P);
 icpcg_status icpcg_prec_destroy(icpcg_prec *P);
 
+/* Fill-in dropout of Eq. 10 (supplementary Additional Results): every
+ * off-diagonal entry of the lower factor L with |l_ij| <= eps becomes a
+ * structural zero and is removed; the diagonal is always kept, and kept
+ * entries keep their order and values. eps >= 0 is absolute (the caller
+ * scales it, e.g. by sqrt(s) to threshold in the network's scaled units).
+ * Outputs are caller-owned device buffers sized for L (row_ptr n + 1, col and
+ * val nnz(L)); *nnz_out (host) receives the kept count. Synchronizes the
+ * stream. Errors: ICPCG_E_INVALID (L not a valid lower factor, eps < 0). */
+icpcg_status icpcg_dropout(icpcg_ctx *ctx, const icpcg_csr *L, double eps, int64_t *row_ptr,
+                           int32_t *col, double *val, int64_t *nnz_out);
+
 /* Replace the factor's values (same pattern, FP64, CSR order of L) and
  * refresh L^T and the reduced-precision copy. */
 icpcg_status icpcg_prec_update_values(icpcg_ctx *ctx, icpcg_prec *P, const double *L_val);

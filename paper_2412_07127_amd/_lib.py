@@ -81,6 +81,7 @@ def load():
         "icpcg_factor": ([P, C.POINTER(Csr), P, P, P, C.POINTER(FactorOpts), C.POINTER(FactorInfo)], st),
         "icpcg_prec_create": ([P, C.POINTER(Csr), st, C.POINTER(P)], st),
         "icpcg_prec_destroy": ([P], st),
+        "icpcg_dropout": ([P, C.POINTER(Csr), C.c_double, P, P, P, C.POINTER(i64)], st),
         "icpcg_prec_create_simple": ([P, C.POINTER(Csr), st, C.POINTER(P)], st),
         "icpcg_prec_update_values": ([P, P, P], st),
         "icpcg_prec_get_info": ([P, P, C.POINTER(PrecInfo)], st),

@@ -346,6 +346,18 @@ icpcg_status icpcg_prec_create_simple(icpcg_ctx *ctx, const icpcg_csr *A, icpcg_
   return ICPCG_OK;
 }
 
+icpcg_status icpcg_dropout(icpcg_ctx *ctx, const icpcg_csr *L, double eps, int64_t *row_ptr, int32_t *col,
+                           double *val, int64_t *nnz_out) {
+  if (!ctx || !valid_csr_args(L) || !(eps >= 0.0) || !nnz_out || (L->n > 0 && (!row_ptr || !col || !val)))
+    return fail(ctx, ICPCG_E_INVALID, "dropout: bad arguments");
+  *nnz_out = 0;
+  if (L->n == 0) return ICPCG_OK;
+  int st = check_matrix(ctx, L, 1);
+  if (st) return finish(ctx, st);
+  return finish(ctx, dropout(L->row_ptr, L->col, (const double *)L->val, L->n, eps, row_ptr, col, val, nnz_out,
+                             ctx->stream));
+}
+
 icpcg_status icpcg_prec_destroy(icpcg_prec *P) {
   delete P;
   return ICPCG_OK;

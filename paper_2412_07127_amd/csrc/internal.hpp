@@ -179,6 +179,9 @@ int tril_count(const int64_t *rp, const int32_t *ci, int64_t n, int64_t *cnt, hi
 int tril_copy(const int64_t *rp, const int32_t *ci, const double *v, int64_t n,
               const int64_t *lrp, int32_t *lci, double *lv, hipStream_t s);
 int build_transpose(icpcg_prec *P, hipStream_t s);
+// Fill-in dropout of a lower CSR factor into (orp, oci, ov); *nnz_host gets the kept count.
+int dropout(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, double eps, int64_t *orp,
+            int32_t *oci, double *ov, int64_t *nnz_host, hipStream_t s);
 int refresh_values(icpcg_prec *P, hipStream_t s);
 int build_schedule(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int smax,
                    TriSchedule &out, hipStream_t s, const Device &dev);

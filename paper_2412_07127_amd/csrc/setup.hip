@@ -432,10 +432,6 @@ int refresh_values(icpcg_prec *P, hipStream_t s) {
   return ICPCG_OK;
 }
 
-// Supernode schedule of a triangular pattern: maximal runs of consecutive
-// rows that share their off-block columns (split into pieces of at most smax
-// rows), with the level of each supernode in the quotient dependency graph
-// and the supernodes sorted by (level, id).
 // Runs of rows flagged by begin[] (1 = starts a new run) split into pieces of
 // at most smax rows: ptr[0..count] row ranges, and (optionally) the piece of
 // every row.
@@ -495,6 +491,50 @@ int build_row_groups(const int64_t *rp, const int32_t *ci, int64_t n, int gmax, 
   hipLaunchKernelGGL(k_group_records, dim3(grid_rows(*ngroups, 4)), dim3(kBlock), 0, s, rp, gptr.as<int32_t>(),
                      *ngroups, grec.as<SpGroup>());
   ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+// Fill-in dropout (Eq. 10): per row, the diagonal and the entries with
+// |l_ij| > eps are kept.
+__global__ void k_drop_count(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                             const double *__restrict__ v, int64_t n, double eps, int64_t *__restrict__ cnt) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t c = 0;
+    for (int64_t t = rp[i]; t < rp[i + 1]; ++t) c += (ci[t] == i || fabs(v[t]) > eps) ? 1 : 0;
+    cnt[i] = c;
+  }
+}
+
+__global__ void k_drop_copy(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                            const double *__restrict__ v, int64_t n, double eps, const int64_t *__restrict__ orp,
+                            int32_t *__restrict__ oci, double *__restrict__ ov) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t o = orp[i];
+    for (int64_t t = rp[i]; t < rp[i + 1]; ++t) {
+      if (ci[t] == i || fabs(v[t]) > eps) {
+        oci[o] = ci[t];
+        ov[o] = v[t];
+        ++o;
+      }
+    }
+  }
+}
+
+int dropout(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, double eps, int64_t *orp,
+            int32_t *oci, double *ov, int64_t *nnz_host, hipStream_t s) {
+  DevBuf cnt;
+  if (cnt.reserve((n + 1) * 8)) return ICPCG_E_NOMEM;
+  hipLaunchKernelGGL(k_drop_count, dim3(grid_rows(n, 4)), dim3(kBlock), 0, s, rp, ci, v, n, eps, cnt.as<int64_t>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  int64_t total = 0;
+  int st = scan_exclusive_i64(cnt.as<int64_t>(), orp, n, s, &total);
+  if (st) return st;
+  hipLaunchKernelGGL(k_set_last_i64, dim3(1), dim3(1), 0, s, orp, n, total);
+  ICPCG_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_drop_copy, dim3(grid_rows(n, 4)), dim3(kBlock), 0, s, rp, ci, v, n, eps, orp, oci, ov);
+  ICPCG_HIP_TRY(hipGetLastError());
+  ICPCG_HIP_TRY(hipStreamSynchronize(s));
+  *nnz_host = total;
   return ICPCG_OK;
 }
 

@@ -182,6 +182,20 @@ class Context:
         self._check(self.lib.icpcg_prec_create(self.h, C.byref(l), DTYPES[dtype], C.byref(h)))
         return Preconditioner(self, h, Lf, dtype)
 
+    def dropout(self, Lf: CSR, eps: float) -> CSR:
+        """Fill-in dropout (Eq. 10): off-diagonal entries with |l| <= eps removed."""
+        self._bind()
+        dev = Lf.val.device
+        rp = torch.empty(Lf.n + 1, dtype=torch.int64, device=dev)
+        ci = torch.empty(Lf.nnz, dtype=torch.int32, device=dev)
+        v = torch.empty(Lf.nnz, dtype=torch.float64, device=dev)
+        cnt = C.c_int64()
+        l = Lf.cstruct()
+        self._check(self.lib.icpcg_dropout(self.h, C.byref(l), float(eps), _ptr(rp), _ptr(ci), _ptr(v),
+                                           C.byref(cnt)))
+        k = cnt.value
+        return CSR(rp, ci[:k].clone(), v[:k].clone())
+
     def prec_simple(self, A: CSR, kind: str) -> "Preconditioner":
         """Table 1's baselines: kind "jacobi" (z_i = r_i / a_ii) or "none" (plain CG)."""
         self._bind()
