@@ -74,13 +74,13 @@ def grouped_pattern(rp, ci, gmax=3):
 
 
 def kernel_bytes(n, nnzA, nnzL, nsn, R, vbytes, rbytes, obytes, ngroups, grouped_cols):
-    """Algorithmic bytes per launch (int32 columns, int64 row pointers, each
-    vector row read once): the row-group SpMV reads A's values, the column
-    indices once per row group, the row pointers and group starts, x, and
-    writes y; a triangular solve reads its factor (value + 4 B column), one
-    16-byte schedule record per supernode, the right-hand side, and writes the
-    solution."""
-    spmv = 8 * nnzA + 4 * grouped_cols + 8 * (n + 1) + 4 * (ngroups + 1) + 16 * n * R
+    """Algorithmic bytes per launch (int32 columns, each vector row read
+    once): the row-group SpMV reads A's values, the column indices once per
+    row group, one 16-byte record per group (offset, first row, length and
+    size), x, and writes y; a triangular solve reads its factor (value + 4 B
+    column), one 16-byte schedule record per supernode, the right-hand side,
+    and writes the solution."""
+    spmv = 8 * nnzA + 4 * grouped_cols + 16 * ngroups + 16 * n * R
     trsv = (vbytes + 4) * nnzL + 16 * nsn + (rbytes + obytes) * n * R
     return spmv, trsv
 

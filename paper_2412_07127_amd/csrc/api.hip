@@ -647,7 +647,7 @@ namespace {
 int reserve_pass(Workspace &ws, int64_t n, int Rb, bool lo, bool gathered) {
   const size_t vec8 = (size_t)n * Rb * 8, vecy = (size_t)n * Rb * (lo ? 4 : 8);
   if (ws.r.reserve(vec8) || ws.p.reserve(vec8) || ws.w.reserve(vec8) || ws.y.reserve(vecy) || ws.z.reserve(vecy) ||
-      ws.partials.reserve((size_t)4096 * Rb * 2 * 8) || ws.cols.reserve(sizeof(ColState) * Rb))
+      ws.partials.reserve((size_t)kMaxDotBlocks * Rb * 2 * 8) || ws.cols.reserve(sizeof(ColState) * Rb))
     return ICPCG_E_NOMEM;
   if (gathered && (ws.tmp0.reserve(vec8) || ws.tmp1.reserve(vec8))) return ICPCG_E_NOMEM;
   return ICPCG_OK;

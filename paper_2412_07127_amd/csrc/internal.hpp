@@ -185,6 +185,10 @@ int dropout(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, do
 int refresh_values(icpcg_prec *P, hipStream_t s);
 int build_schedule(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int smax,
                    TriSchedule &out, hipStream_t s, const Device &dev);
+// Most blocks of a kernel that writes per-block reduction partials (the
+// solve's partials buffer holds kMaxDotBlocks * R * 2 doubles).
+constexpr int64_t kMaxDotBlocks = 32768;
+
 // One row group of A for the SpMV: its first row r0, the CSR offset `base`
 // of that row (the group's rows follow at base + u * m) and (m << 3) | size.
 struct SpGroup {

@@ -201,8 +201,12 @@ template <int R, int SLOTS, int CPL>
 int launch_grp(const int32_t *ci, const double *v, int64_t ngroups, const SpGroup *grec, const double *x, double *y,
                hipStream_t s, double *partials, ColState *cols, const int *active) {
   constexpr int GPB = kBlock / (SLOTS * (R / CPL));
-  int64_t nb = (ngroups + GPB * 8 - 1) / (GPB * 8);
-  if (nb > 4096) nb = 4096;
+  // Short chunks keep the groups in flight on one XCD close together, so its
+  // L2 serves more of the neighbouring x gathers (measured best per width);
+  // the fused p^T w partials bound the block count.
+  constexpr int ITERS = R >= 16 ? 16 : R >= 8 ? 8 : R >= 4 ? 2 : 1;
+  int64_t nb = (ngroups + GPB * ITERS - 1) / (GPB * ITERS);
+  if (partials && nb > kMaxDotBlocks) nb = kMaxDotBlocks;
   if (nb < 1) nb = 1;
   const int64_t chunk = (ngroups + nb - 1) / nb;
   nb = (ngroups + chunk - 1) / chunk;
