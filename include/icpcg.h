@@ -304,6 +304,34 @@ icpcg_status icpcg_solve_mat(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_pre
                              const double *B, double *X, int64_t nrhs,
                              const icpcg_solve_opts *opts, icpcg_col_info *info);
 
+/* ------------------------------------------------ multicolour ordering */
+
+/* A symmetric permutation that exposes parallelism to the triangular solves
+ * (the layout direction of supplementary Additional Results). Nodes are the
+ * row groups of A (consecutive rows with identical column lists, at most 3);
+ * node v (key: SplitMix64(seed + v), then v) takes the smallest colour not
+ * used by its neighbours of higher key (neighbours: the nodes of the columns
+ * its rows store), which is a proper colouring for a structurally symmetric
+ * A. perm (device, n int32, new row -> old row) lists the nodes by (colour,
+ * id), each node's rows in order; *ncolours (host) receives the count.
+ * Factorizing P A P^T then gives at most (colours x rows per node) row
+ * levels. Synchronizes the stream. Errors: ICPCG_E_INVALID (malformed A,
+ * more than 256 colours), ICPCG_E_NOMEM. */
+icpcg_status icpcg_color_order(icpcg_ctx *ctx, const icpcg_csr *A, uint64_t seed, int32_t *perm,
+                               int32_t *ncolours);
+
+/* B = P A P^T (entry (i, j) = A[perm[i], perm[j]]) into caller-owned device
+ * buffers (row_ptr n + 1, col and val nnz(A)), rows with ascending columns.
+ * Synchronizes the stream. Errors: ICPCG_E_INVALID (perm not a permutation,
+ * malformed A). */
+icpcg_status icpcg_permute_matrix(icpcg_ctx *ctx, const icpcg_csr *A, const int32_t *perm,
+                                  int64_t *row_ptr, int32_t *col, double *val);
+
+/* Row-major n x nrhs FP64 blocks: Y[i] = X[perm[i]] (inverse = 0) or
+ * Y[perm[i]] = X[i] (inverse = 1). Stream-ordered; X and Y must not alias. */
+icpcg_status icpcg_permute_rows(icpcg_ctx *ctx, const int32_t *perm, int64_t n, int64_t nrhs,
+                                const double *X, double *Y, int inverse);
+
 /* ------------------------------------------- learned factor correction */
 
 /* The correction of Eq. 2, L_pred = L_IC + GNN(A), with the network of the

@@ -98,6 +98,9 @@ def load():
         "icpcg_mat_spmv": ([P, P, P, P, i64], st),
         "icpcg_solve_mat": ([P, P, P, P, P, i64, C.POINTER(SolveOpts), C.POINTER(ColInfo)], st),
         "icpcg_autotune": ([P, P, P, i64, C.POINTER(TuneInfo)], st),
+        "icpcg_color_order": ([P, C.POINTER(Csr), C.c_uint64, P, C.POINTER(C.c_int32)], st),
+        "icpcg_permute_matrix": ([P, C.POINTER(Csr), P, P, P, P], st),
+        "icpcg_permute_rows": ([P, P, i64, i64, P, P, st], st),
         "icpcg_gnn_num_params": ([], i64),
         "icpcg_gnn_create": ([P, C.POINTER(Csr), P, C.POINTER(P)], st),
         "icpcg_gnn_destroy": ([P], st),

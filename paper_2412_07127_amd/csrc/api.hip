@@ -953,3 +953,35 @@ extern "C" icpcg_status icpcg_adam_step(icpcg_ctx *ctx, double *theta, const dou
   if (count == 0) return ICPCG_OK;
   return finish(ctx, adam_step(theta, grad, m, v, count, t, lr, beta1, beta2, eps, ctx->stream));
 }
+
+// ------------------------------------------------------ multicolour ordering
+
+extern "C" icpcg_status icpcg_color_order(icpcg_ctx *ctx, const icpcg_csr *A, uint64_t seed, int32_t *perm,
+                                          int32_t *ncolours) {
+  if (!ctx || !valid_csr_args(A) || !ncolours || (A->n > 0 && !perm))
+    return fail(ctx, ICPCG_E_INVALID, "color_order: bad arguments");
+  *ncolours = 0;
+  if (A->n == 0) return ICPCG_OK;
+  int st = check_matrix(ctx, A, 0);
+  if (st) return finish(ctx, st);
+  return finish(ctx, color_order(A->row_ptr, A->col, A->n, seed, perm, ncolours, ctx->stream));
+}
+
+extern "C" icpcg_status icpcg_permute_matrix(icpcg_ctx *ctx, const icpcg_csr *A, const int32_t *perm,
+                                             int64_t *row_ptr, int32_t *col, double *val) {
+  if (!ctx || !valid_csr_args(A) || (A->n > 0 && (!perm || !row_ptr || !col || !val)) || A->nnz >= (int64_t{1} << 32))
+    return fail(ctx, ICPCG_E_INVALID, "permute_matrix: bad arguments");
+  if (A->n == 0) return ICPCG_OK;
+  int st = check_matrix(ctx, A, 0);
+  if (st) return finish(ctx, st);
+  return finish(ctx, permute_matrix(A->row_ptr, A->col, (const double *)A->val, A->n, A->nnz, perm, row_ptr, col, val,
+                                    ctx->stream));
+}
+
+extern "C" icpcg_status icpcg_permute_rows(icpcg_ctx *ctx, const int32_t *perm, int64_t n, int64_t nrhs,
+                                           const double *X, double *Y, int inverse) {
+  if (!ctx || n < 0 || nrhs < 1 || (n > 0 && (!perm || !X || !Y)) || X == Y)
+    return fail(ctx, ICPCG_E_INVALID, "permute_rows: bad arguments");
+  if (n == 0) return ICPCG_OK;
+  return finish(ctx, permute_rows(perm, n, nrhs, X, Y, inverse != 0, ctx->stream));
+}

@@ -196,6 +196,36 @@ class Context:
         k = cnt.value
         return CSR(rp, ci[:k].clone(), v[:k].clone())
 
+    def color_order(self, A: CSR, seed: int = 0):
+        """Multicolour node order: (perm int32 tensor, new row -> old row; colour count)."""
+        self._bind()
+        perm = torch.empty(A.n, dtype=torch.int32, device=A.val.device)
+        nc = C.c_int32()
+        a = A.cstruct()
+        self._check(self.lib.icpcg_color_order(self.h, C.byref(a), C.c_uint64(seed), _ptr(perm), C.byref(nc)))
+        return perm, nc.value
+
+    def permute(self, A: CSR, perm: torch.Tensor) -> CSR:
+        """P A P^T."""
+        self._bind()
+        dev = A.val.device
+        out = CSR(torch.empty(A.n + 1, dtype=torch.int64, device=dev), torch.empty(A.nnz, dtype=torch.int32, device=dev),
+                  torch.empty(A.nnz, dtype=torch.float64, device=dev))
+        a = A.cstruct()
+        self._check(self.lib.icpcg_permute_matrix(self.h, C.byref(a), _ptr(perm), _ptr(out.row_ptr), _ptr(out.col),
+                                                  _ptr(out.val)))
+        return out
+
+    def permute_rows(self, perm: torch.Tensor, X: torch.Tensor, inverse: bool = False) -> torch.Tensor:
+        """Y[i] = X[perm[i]] (or the inverse scatter) for an n-vector or n x R block."""
+        self._bind()
+        Xc = X.contiguous()
+        R = _block_width(Xc, perm.numel(), torch.float64)
+        Y = torch.empty_like(Xc)
+        self._check(self.lib.icpcg_permute_rows(self.h, _ptr(perm), perm.numel(), R, _ptr(Xc), _ptr(Y),
+                                                int(bool(inverse))))
+        return Y
+
     def prec_simple(self, A: CSR, kind: str) -> "Preconditioner":
         """Table 1's baselines: kind "jacobi" (z_i = r_i / a_ii) or "none" (plain CG)."""
         self._bind()
