@@ -6,10 +6,13 @@ sigma = 2.0, nu = 0.3. IC(0) is computed in FP64 on the GPU; PCG runs to a
 relative residual of 1e-8 with a true-residual check.
 
 A timed step is one multi-RHS solve of 16 load cases (body load plus a
-seeded random traction on the top face) with the factor applied in FP32 and
-FP64 recurrences. The value is solved right-hand sides per second over the
-timed steps (inputs resident in HBM). Single-RHS solves in FP64, FP32-L and
-BF16-L are reported beside it, with the factor (P-time) separately.
+seeded random traction on the top face) with the IC(0) factor applied in
+FP32 and FP64 recurrences. The value is solved right-hand sides per second
+over the timed steps (inputs resident in HBM). Reported beside it:
+single-RHS solves in FP64, FP32-L and BF16-L, and the multicolour node order
+(the right-hand sides permuted in and the solutions back inside the timing)
+for one FP64 solve and one 16-RHS step, with the factors (P-time) and the
+ordering time separately.
 
 One JSON line on stdout; progress on stderr.
 """
@@ -184,13 +187,16 @@ def main():
     M = ctx.matrix(A)  # row-group analysis, once (as the solver uses it)
     torch.cuda.synchronize()
 
-    # P-time: IC(0) in FP64 (second call timed; the first loads code objects)
-    ctx.factor(A)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Lf, finfo = ctx.factor(A)
-    torch.cuda.synchronize()
-    p_time = time.perf_counter() - t0
+    def timed_factor(Am):
+        ctx.factor(Am)  # the first call loads code objects
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        Lx, fi = ctx.factor(Am)
+        torch.cuda.synchronize()
+        return Lx, fi, time.perf_counter() - t
+
+    # natural order: IC(0) in FP64 (P-time)
+    Lf, finfo, p_time = timed_factor(A)
     log(f"factor: {p_time:.3f} s alpha={finfo['alpha']} restarts={finfo['restarts']} levels={finfo['nlevels']}")
     t0 = time.perf_counter()
     P64 = ctx.prec(Lf, "f64")
@@ -199,6 +205,22 @@ def main():
     prec_time = (time.perf_counter() - t0) / 2
     pinfo = P32.info()
     log(f"prec setup {prec_time:.3f} s; schedule {pinfo}")
+
+    # multicolour node order: colouring, P A P^T, IC(0) of the permuted matrix
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    perm, ncol = ctx.color_order(A, seed=0)
+    Ac = ctx.permute(A, perm)
+    torch.cuda.synchronize()
+    order_time = time.perf_counter() - t0
+    Mc = ctx.matrix(Ac)
+    Lc, finfo_c, p_time_c = timed_factor(Ac)
+    Pc64 = ctx.prec(Lc, "f64")
+    Pc32 = ctx.prec(Lc, "f32")
+    pinfo_c = Pc32.info()
+    log(f"multicolour: {ncol} colours, ordering {order_time:.3f} s, factor {p_time_c:.3f} s, "
+        f"alpha={finfo_c['alpha']}, supernode levels {pinfo_c['nsn_levels_L']}")
+    del Lf, Lc
 
     bt = torch.from_numpy(b).cuda()
     Bt = torch.from_numpy(B).cuda()
@@ -217,10 +239,18 @@ def main():
                           "copy_bytes_each_way": src.numel() * 8}), flush=True)
         return
 
-    def run_single(P, name):
+    def solve_in(order, Mx, Px, rhs):
+        """One solve of the original system: in the multicolour order the right-
+        hand sides are permuted in and the solution back (inside the timing)."""
+        if order == "natural":
+            return ctx.solve(Mx, Px, rhs, rtol=args.rtol)
+        Xp, info = ctx.solve(Mx, Px, ctx.permute_rows(perm, rhs), rtol=args.rtol)
+        return ctx.permute_rows(perm, Xp, inverse=True), info
+
+    def run_single(order, Mx, Px, name):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        X, info = ctx.solve(M, P, bt, rtol=args.rtol)
+        X, info = solve_in(order, Mx, Px, bt)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         i = info[0]
@@ -230,39 +260,48 @@ def main():
         return X
 
     if not args.skip_single:
-        x64 = run_single(P64, "fp64")
-        x32 = run_single(P32, "fp32_L")
-        Pb = ctx.prec(Lf, "bf16")
-        xb = run_single(Pb, "bf16_L")
+        x64 = run_single("natural", M, P64, "fp64")
+        x32 = run_single("natural", M, P32, "fp32_L")
+        Pb = ctx.prec(P64.L, "bf16")
+        xb = run_single("natural", M, Pb, "bf16_L")
+        xc = run_single("colour", Mc, Pc64, "fp64_multicolour")
         nx = torch.linalg.norm(x64).item()
-        variants["fp32_L"]["rel_diff_vs_fp64_gpu"] = torch.linalg.norm(x32 - x64).item() / nx
-        variants["bf16_L"]["rel_diff_vs_fp64_gpu"] = torch.linalg.norm(xb - x64).item() / nx
+        for name, xx in (("fp32_L", x32), ("bf16_L", xb), ("fp64_multicolour", xc)):
+            variants[name]["rel_diff_vs_fp64_gpu"] = torch.linalg.norm(xx - x64).item() / nx
         del Pb
 
-    # headline: 16 load cases, FP32 factor, FP64 recurrences
-    for w in range(args.warmup):
-        ctx.solve(M, P32, Bt, rtol=args.rtol)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = None
-    for k in range(args.steps):
-        X, infos = ctx.solve(M, P32, Bt, rtol=args.rtol)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    step_s = total / args.steps
-    iters = [i["iters"] for i in infos]
-    tr = [i["true_relres"] for i in infos]
-    st = [i["status"] for i in infos]
+    def multi(order, Mx, Px, name, steps, warmup):
+        ctx.autotune(Mx, Px, args.nrhs)  # the width choice is setup, outside the timing
+        for _ in range(warmup):
+            solve_in(order, Mx, Px, Bt)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        infos = None
+        for _ in range(steps):
+            X, infos = solve_in(order, Mx, Px, Bt)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t
+        step_s = total / steps
+        iters = [i["iters"] for i in infos]
+        tr = [i["true_relres"] for i in infos]
+        variants[name] = dict(step_s=step_s, per_rhs_s=step_s / args.nrhs, rhs_per_s=args.nrhs * steps / total,
+                              iters_max=max(iters), iters_min=min(iters), true_relres_max=max(tr),
+                              statuses=sorted(set(i["status"] for i in infos)))
+        log(f"{name}: {step_s:.3f} s/step ({args.nrhs} RHS), iters {min(iters)}..{max(iters)}, "
+            f"max true relres {max(tr):.2e}")
+        return total, step_s
+
+    # multicolour order, 16 load cases (reported beside the headline)
+    if not args.skip_single:
+        multi("colour", Mc, Pc32, "multi16_fp32_L_multicolour", 1, 0)
+    # headline: natural order, 16 load cases, FP32 factor, FP64 recurrences
+    total, step_s = multi("natural", M, P32, "multi16_fp32_L", args.steps, args.warmup)
     value = args.nrhs * args.steps / total
-    variants["multi16_fp32_L"] = dict(step_s=step_s, per_rhs_s=step_s / args.nrhs, iters_max=max(iters),
-                                      iters_min=min(iters), true_relres_max=max(tr), statuses=sorted(set(st)))
-    log(f"multi-RHS: {step_s:.3f} s/step ({args.nrhs} RHS), iters {min(iters)}..{max(iters)}, "
-        f"max true relres {max(tr):.2e}")
 
     # per-kernel live timing at the headline's launch shape
     R = args.nrhs if args.nrhs in (1, 2, 4, 8, 16) else 16
     kt = time_kernels(ctx, M, P32, R, args.kernel_reps, torch)
-    n, nnzA, nnzL = prob.n, prob.nnz, Lf.nnz
+    n, nnzA, nnzL = prob.n, prob.nnz, pinfo["nnz"]
     ngroups, gcols = grouped_pattern(prob.row_ptr, prob.col)
     nsnL, nsnU = pinfo["nsupernodes_L"], pinfo["nsupernodes_U"]
     spmv_b, trsvL_b = kernel_bytes(n, nnzA, nnzL, nsnL, R, 4, 8, 4, ngroups, gcols)
@@ -281,7 +320,7 @@ def main():
 
     cpu = None
     if not args.skip_cpu:
-        k64 = variants.get("fp64", {}).get("iters", max(iters))
+        k64 = variants.get("fp64", {}).get("iters", 800)
         log("CPU oracle baseline ...")
         cpu = cpu_baseline(prob, b, k64)
         log(f"cpu baseline: {cpu['sample']}")
@@ -303,16 +342,21 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"Q1 elasticity {E}^3 elements, {n} DOF, nnz {nnzA}, sigma={sigma}; "
-                         f"{args.nrhs} load cases per step; IC(0) FP64 on GPU, factor applied in FP32; "
-                         f"rtol {args.rtol} (true residual)"),
+                         f"{args.nrhs} load cases per step; IC(0) FP64 on GPU (natural order), factor applied "
+                         f"in FP32; rtol {args.rtol} (true residual)"),
             "nrhs": args.nrhs, "block_width": R, "n": n, "nnz_A": nnzA, "nnz_L": nnzL,
         },
         "roofline": roof,
         "cpu_baseline": cpu,
         "p_time_s": round(p_time, 4),
+        "p_time_multicolour_s": round(p_time_c, 4),
+        "ordering_s": round(order_time, 4),
         "prec_setup_s": round(prec_time, 4),
         "factor": dict(alpha=finfo["alpha"], restarts=finfo["restarts"], row_levels=finfo["nlevels"],
                        supernode_levels_L=pinfo["nsn_levels_L"], supernode_levels_U=pinfo["nsn_levels_U"]),
+        "factor_multicolour": dict(alpha=finfo_c["alpha"], restarts=finfo_c["restarts"],
+                                   row_levels=finfo_c["nlevels"], supernode_levels_L=pinfo_c["nsn_levels_L"],
+                                   supernode_levels_U=pinfo_c["nsn_levels_U"]),
         "variants": variants,
         "kernels": {k_: dict(ms=round(v["s"] * 1e3, 4), algorithmic_GBs=round(v["gbs"], 1),
                              bytes=v["bytes"]) for k_, v in kernels.items()},
