@@ -24,10 +24,11 @@
 //    lanes covering one pending row poll its columns (with a short backoff)
 //    before the pending ones are loaded again, so thousands of waiting waves
 //    do not flood the memory system and a ready input costs one round trip.
-//  * Lanes of a wave are (slot, column): R lanes cover one gathered row of
-//    the row-major block, so every device-scope load and every publish is
-//    one contiguous row per instruction (full-line requests, no partial-line
-//    writes), and the 64 / R slots stride over the off-block entries.
+//  * Lanes of a wave are (slot, column group): a lane owns CPL consecutive
+//    columns (1, or 2 from 8 columns up) and R / CPL lanes cover one gathered
+//    row of the row-major block, so every device-scope load and every publish
+//    is one contiguous row per instruction (full-line requests, no
+//    partial-line writes); the slots stride over the off-block entries.
 //    Partial sums meet in a fixed butterfly (deterministic).
 //  * Factor values may be FP64, FP32 or bfloat16 (widened to FP32); FP32 and
 //    bfloat16 factors run FP32 arithmetic.
@@ -55,20 +56,58 @@ __device__ __forceinline__ int64_t row_start(int64_t ro0, int u, int m, int sz) 
                : ro0 + (int64_t)u * (m + 1) + (int64_t)u * (u - 1) / 2;
 }
 
-template <typename TV, typename TA, typename TR, int R, bool UPPER, int QD>
+// CPL consecutive elements of a row at p, each read with a device-scope load
+// (a pair of FP32 values in one 8-byte load). Each element keeps its own
+// pending pattern, so a reader never needs the pair to change at once.
+template <typename TA, int CPL>
+__device__ __forceinline__ void load_elems(const TA *p, typename Flag<TA>::U (&e)[CPL]) {
+  using U = typename Flag<TA>::U;
+  if constexpr (CPL == 2 && sizeof(U) == 4) {
+    const unsigned long long v = ld_agent(reinterpret_cast<const unsigned long long *>(p));
+    e[0] = (U)v;
+    e[1] = (U)(v >> 32);
+  } else {
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) e[cc] = ld_agent(reinterpret_cast<const U *>(p) + cc);
+  }
+}
+
+template <typename TA, int CPL>
+__device__ __forceinline__ bool any_pending(const typename Flag<TA>::U (&e)[CPL]) {
+  bool pd = false;
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) pd |= e[cc] == Flag<TA>::kPending;
+  return pd;
+}
+
+template <typename TA, int CPL>
+__device__ __forceinline__ void publish_elems(TA *p, const TA (&x)[CPL]) {
+  using U = typename Flag<TA>::U;
+  if constexpr (CPL == 2 && sizeof(U) == 4) {
+    U lo = bitcast<U>(x[0]), hi = bitcast<U>(x[1]);
+    if (lo == Flag<TA>::kPending) lo = Flag<TA>::kCanonNaN;
+    if (hi == Flag<TA>::kPending) hi = Flag<TA>::kCanonNaN;
+    st_agent(reinterpret_cast<unsigned long long *>(p), (unsigned long long)lo | ((unsigned long long)hi << 32));
+  } else {
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) publish_value<TA>(p + cc, x[cc]);
+  }
+}
+
+template <typename TV, typename TA, typename TR, int R, bool UPPER, int QD, int CPL>
 __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci, const TV *__restrict__ val,
                                                  const SnItem *__restrict__ sched, int64_t nsn,
                                                  const TR *__restrict__ rhs, TA *out, int *err, long long limit,
                                                  const int *__restrict__ active) {
   if (active && *active == 0) return;  // every column of the solve has stopped
   using U = typename Flag<TA>::U;
-  constexpr U kPend = Flag<TA>::kPending;
-  constexpr int SLOTS = 64 / R;                  // entry slots per wave; R lanes per gathered row
+  constexpr int LPR = R / CPL;                   // lanes per gathered row
+  constexpr int SLOTS = 64 / LPR;                // entry slots per wave
   constexpr int NDB = kSmax * (kSmax + 1) / 2;  // stored entries of a dense diagonal block
-  const int lane = threadIdx.x & 63, slot = lane / R, c = lane % R;
+  constexpr unsigned long long kRowMask = LPR >= 64 ? ~0ull : ((1ull << LPR) - 1);
+  const int lane = threadIdx.x & 63, slot = lane / LPR, c0 = (lane % LPR) * CPL;
   const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
-  const U *outb = reinterpret_cast<const U *>(out);
   SnItem nxt;
   if (w0 < nsn) nxt = sched[w0];
   for (int64_t t = w0; t < nsn; t += nw) {
@@ -93,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
         vv[k][u] = (q < m && u < sz) ? widen<TA>(val[UPPER ? ro[u] + (sz - u) + q : ro[u] + q]) : TA(0);
     }
     TA dv[NDB];  // diagonal block, row by row (lower: columns a..a+u; upper: a+u..a+sz-1)
-    TA bv[kSmax];
+    TA bv[kSmax][CPL];
     if (slot == 0) {
 #pragma unroll
       for (int u = 0; u < kSmax; ++u) {
@@ -106,24 +145,30 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
           for (int w = 0; w < kSmax - u; ++w)
             dv[u * kSmax - u * (u - 1) / 2 + w] = (u < sz && w < sz - u) ? widen<TA>(val[ro[u] + w]) : TA(1);
         }
-        bv[u] = u < sz ? (TA)rhs[(int64_t)(a + u) * R + c] : TA(0);
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) bv[u][cc] = u < sz ? (TA)rhs[(int64_t)(a + u) * R + c0 + cc] : TA(0);
       }
     }
     // gather the dependencies: one attempt for all, then while any is still
-    // pending the R lanes covering one pending row poll it together (one
+    // pending the lanes covering one pending row poll it together (one
     // contiguous row per load) and the pending ones are loaded again
-    U xb[QD];
+    U xb[QD][CPL];
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
       const int q = slot + k * SLOTS;
-      xb[k] = q < m ? ld_agent(outb + (int64_t)jj[k] * R + c) : (U)0;
+      if (q < m) {
+        load_elems<TA, CPL>(out + (int64_t)jj[k] * R + c0, xb[k]);
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) xb[k][cc] = 0;
+      }
     }
     for (;;) {
       bool pend = false;
       int pk = 0;
 #pragma unroll
       for (int k = QD - 1; k >= 0; --k)
-        if (xb[k] == kPend) { pend = true; pk = k; }
+        if (any_pending<TA, CPL>(xb[k])) { pend = true; pk = k; }
       const unsigned long long mask = __ballot(pend);
       if (!mask) break;
       const int leader = 63 - __clzll(mask);  // the nearest rows sit last
@@ -134,79 +179,97 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
 #pragma unroll
         for (int k = 0; k < QD; ++k)
           if (k == pkk) jp = jj[k];
-        const U *p = outb + (int64_t)jp * R + c;
-        U v = ld_agent(p);
+        const TA *p = out + (int64_t)jp * R + c0;
+        U v[CPL];
+        load_elems<TA, CPL>(p, v);
         const long long t0 = wall_clock64();
         int backoff = 1;
-        while (__ballot(v == kPend) & (((1ull << R) - 1) << (pslot * R))) {
+        while (__ballot(any_pending<TA, CPL>(v)) & (kRowMask << (pslot * LPR))) {
           for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(1);
           if (backoff < 4) backoff <<= 1;
-          if (v == kPend) v = ld_agent(p);
-          if (wall_clock64() - t0 > limit) {
-            if (v == kPend) {
-              __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              v = Flag<TA>::kCanonNaN;
-            }
+          if (any_pending<TA, CPL>(v)) load_elems<TA, CPL>(p, v);
+          if (wall_clock64() - t0 > limit && any_pending<TA, CPL>(v)) {
+            __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+            for (int cc = 0; cc < CPL; ++cc)
+              if (v[cc] == Flag<TA>::kPending) v[cc] = Flag<TA>::kCanonNaN;
           }
         }
 #pragma unroll
         for (int k = 0; k < QD; ++k)
-          if (k == pkk) xb[k] = v;
+          if (k == pkk) {
+#pragma unroll
+            for (int cc = 0; cc < CPL; ++cc) xb[k][cc] = v[cc];
+          }
       }
 #pragma unroll
       for (int k = 0; k < QD; ++k)
-        if (xb[k] == kPend) xb[k] = ld_agent(outb + (int64_t)jj[k] * R + c);
+        if (any_pending<TA, CPL>(xb[k])) load_elems<TA, CPL>(out + (int64_t)jj[k] * R + c0, xb[k]);
     }
-    TA acc[kSmax];
+    TA acc[kSmax][CPL];
 #pragma unroll
-    for (int u = 0; u < kSmax; ++u) acc[u] = TA(0);
+    for (int u = 0; u < kSmax; ++u)
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) acc[u][cc] = TA(0);
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
       const int q = slot + k * SLOTS;
       if (q < m) {
-        const TA x = bitcast<TA>(xb[k]);
 #pragma unroll
-        for (int u = 0; u < kSmax; ++u) acc[u] += vv[k][u] * x;
+        for (int cc = 0; cc < CPL; ++cc) {
+          const TA x = bitcast<TA>(xb[k][cc]);
+#pragma unroll
+          for (int u = 0; u < kSmax; ++u) acc[u][cc] += vv[k][u] * x;
+        }
       }
     }
     // rows longer than the prefetch window
     for (int q = slot + QD * SLOTS; q < m; q += SLOTS) {
-      const TA x = wait_value<TA>(out + (int64_t)ci[pcol + q] * R + c, err, limit);
+      const int64_t jr = (int64_t)ci[pcol + q] * R + c0;
 #pragma unroll
-      for (int u = 0; u < kSmax; ++u)
-        if (u < sz) acc[u] += widen<TA>(val[UPPER ? ro[u] + (sz - u) + q : ro[u] + q]) * x;
+      for (int cc = 0; cc < CPL; ++cc) {
+        const TA x = wait_value<TA>(out + jr + cc, err, limit);
+#pragma unroll
+        for (int u = 0; u < kSmax; ++u)
+          if (u < sz) acc[u][cc] += widen<TA>(val[UPPER ? ro[u] + (sz - u) + q : ro[u] + q]) * x;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < kSmax; ++u) acc[u] = xor_sum_hi<Log2<R>::v>(acc[u]);
+    for (int u = 0; u < kSmax; ++u)
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) acc[u][cc] = xor_sum_hi<Log2<LPR>::v>(acc[u][cc]);
     if (slot == 0) {
-      TA xs[kSmax];
-      if (!UPPER) {
+      TA xs[kSmax][CPL];
 #pragma unroll
-        for (int u = 0; u < kSmax; ++u) {
-          if (u < sz) {
-            TA sum = bv[u] - acc[u];
+      for (int cc = 0; cc < CPL; ++cc) {
+        if (!UPPER) {
 #pragma unroll
-            for (int w = 0; w < u; ++w) sum -= dv[u * (u + 1) / 2 + w] * xs[w];
-            xs[u] = sum / dv[u * (u + 1) / 2 + u];
+          for (int u = 0; u < kSmax; ++u) {
+            if (u < sz) {
+              TA sum = bv[u][cc] - acc[u][cc];
+#pragma unroll
+              for (int w = 0; w < u; ++w) sum -= dv[u * (u + 1) / 2 + w] * xs[w][cc];
+              xs[u][cc] = sum / dv[u * (u + 1) / 2 + u];
+            }
           }
-        }
-      } else {
+        } else {
 #pragma unroll
-        for (int uu = kSmax - 1; uu >= 0; --uu) {
-          if (uu < sz) {
-            const int base = uu * kSmax - uu * (uu - 1) / 2;  // (uu, uu) in the upper storage
-            TA sum = bv[uu] - acc[uu];
+          for (int uu = kSmax - 1; uu >= 0; --uu) {
+            if (uu < sz) {
+              const int base = uu * kSmax - uu * (uu - 1) / 2;  // (uu, uu) in the upper storage
+              TA sum = bv[uu][cc] - acc[uu][cc];
 #pragma unroll
-            for (int w = uu + 1; w < kSmax; ++w)
-              if (w < sz) sum -= dv[base + (w - uu)] * xs[w];
-            xs[uu] = sum / dv[base];
+              for (int w = uu + 1; w < kSmax; ++w)
+                if (w < sz) sum -= dv[base + (w - uu)] * xs[w][cc];
+              xs[uu][cc] = sum / dv[base];
+            }
           }
         }
       }
       // one contiguous row of R values per store instruction
 #pragma unroll
       for (int u = 0; u < kSmax; ++u)
-        if (u < sz) publish_value<TA>(out + (int64_t)(a + u) * R + c, xs[u]);
+        if (u < sz) publish_elems<TA, CPL>(out + (int64_t)(a + u) * R + c0, xs[u]);
     }
   }
 }
@@ -231,16 +294,25 @@ int64_t resident_blocks(K kernel, const Device &dev, int &cached) {
   return (int64_t)per_cu * dev.num_cu;
 }
 
-// Prefetch window (entries per lane) so that SLOTS x depth >= 40 covers the 39
+// Columns per lane: two for FP64 solves from 8 columns up, which halves the
+// prefetch arrays (3 instead of 2 resident waves per SIMD for this
+// latency-bound kernel) while R / 2 lanes still cover a gathered row with one
+// contiguous request; FP32 solves keep one (measured: the pair layout
+// streams faster but lengthens each dependency hop more than it gains).
+template <typename TA, int R> struct Cpl { static constexpr int v = (sizeof(TA) == 8 && R >= 8) ? 2 : 1; };
+// Prefetch window (entries per lane) so that slots x depth >= 40 covers the 39
 // shared off-block entries of a 3-DOF elasticity node; longer rows go
 // through the (slower) remainder loop.
-template <int R> struct Depth { static constexpr int v = (40 + 64 / R - 1) / (64 / R); };
+template <typename TA, int R> struct Depth {
+  static constexpr int slots = 64 / (R / Cpl<TA, R>::v);
+  static constexpr int v = (40 + slots - 1) / slots;
+};
 
 template <typename TV, typename TA, typename TR, int R, bool UPPER>
 int launch(const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs, TA *out, hipStream_t s,
            const Device &dev, int *err, const int *active) {
   if (S.nsn == 0) return ICPCG_OK;
-  auto k = k_trsv<TV, TA, TR, R, UPPER, Depth<R>::v>;
+  auto k = k_trsv<TV, TA, TR, R, UPPER, Depth<TA, R>::v, Cpl<TA, R>::v>;
   static int per_cu = 0;  // occupancy of this instantiation (same on every MI355X)
   int64_t grid = resident_blocks(k, dev, per_cu);
   const int64_t need = (S.nsn + 3) / 4;
