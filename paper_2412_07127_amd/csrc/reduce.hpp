@@ -61,15 +61,30 @@ __device__ __forceinline__ void block_partials_cpl(const double (&v)[CPL], doubl
 }
 
 // In the one-block finalize kernel: out[k * R + c] = sum over the nb blocks'
-// partials, folded in block order. Must be called by every thread.
+// partials in a fixed order: thread t takes blocks t / R + j * (256 / R), into
+// 8 accumulators by j mod 8 (8 independent loads in flight), combined in
+// order, then the block tree. Must be called by every thread.
 template <int R, int K>
 __device__ __forceinline__ void fold_partials(const double *partials, int nb, double *smem, double *out) {
   const int t = threadIdx.x;
   const int c = t % R;
+  constexpr int STEP = kRedBlock / R;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
+    double a8[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a8[j] = 0.0;
+    int b = t / R;
+    for (; b + 7 * STEP < nb; b += 8 * STEP) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a8[j] += partials[((int64_t)(b + j * STEP) * K + k) * R + c];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (b + j * STEP < nb) a8[j] += partials[((int64_t)(b + j * STEP) * K + k) * R + c];
     double acc = 0.0;
-    for (int b = t / R; b < nb; b += kRedBlock / R) acc += partials[((int64_t)b * K + k) * R + c];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += a8[j];
     smem[k * kRedBlock + t] = acc;
   }
   __syncthreads();
