@@ -33,6 +33,15 @@
  *     boundary. icpcg_last_error() gives a message for the last failing call on
  *     a context.
  *   - A context is not thread-safe; use one per host thread.
+ *
+ * Tuning knobs (environment, read when a context is created or a kernel is
+ * first chosen; the defaults are the measured best on MI355X):
+ *   ICPCG_TRSV_WAVES_PER_CU  cap on the resident waves per CU of the
+ *                            triangular solves (default: all that fit)
+ *   ICPCG_SPMVG_SLOTS        entry slots per row group of the grouped SpMV
+ *                            (16 or 32; default 32 below 8 columns, else 16)
+ *   ICPCG_SPMV_SLOTS         entry slots per row of the plain SpMV (default 16)
+ *   ICPCG_NO_ROW_GROUPS      when set, analysed matrices use the plain SpMV
  */
 #ifndef ICPCG_H
 #define ICPCG_H
