@@ -175,10 +175,10 @@ def main():
     torch.cuda.set_device(0)
     E, sigma = args.E, args.sigma
     t0 = time.perf_counter()
-    w = WORKLOADS["q1_100"]
-    same = (E, sigma) == (w["E"], w["sigma"])
-    prob = q1_elasticity(E, sigma, w["seed_A"] if same else 1000 + E)
-    b = body_load(E, 0.1, w["seed_b"] if same else 2000 + E)
+    # the named workload of this size, if any (its seeds), else seeds from E
+    w = next((v for v in WORKLOADS.values() if (v["E"], v["sigma"]) == (E, sigma)), None)
+    prob = q1_elasticity(E, sigma, w["seed_A"] if w else 1000 + E)
+    b = body_load(E, 0.1, w["seed_b"] if w else 2000 + E)
     B = traction_loads(E, args.nrhs, WORKLOADS["q1_150_loads16"]["seed_b"])
     log(f"generated E={E}: n={prob.n} nnz={prob.nnz} ({time.perf_counter() - t0:.1f} s)")
 
@@ -318,6 +318,33 @@ def main():
                 frac=round(kernels[dom]["gbs"] / PEAK_HBM_GBS, 4), traffic=recorded_traffic(dom),
                 algorithmic_bytes_per_launch=kernels[dom]["bytes"], launch_ms=round(kernels[dom]["s"] * 1e3, 4))
 
+    # the learned correction at this scale: one forward (inference) and one
+    # loss + gradient pass (a training step's work) over nnz(L) edges
+    gnn = None
+    if not args.skip_single:
+        from paper_2412_07127_amd import gnn as G
+        g = G.GNNGraph(ctx, A, P64)
+        theta = G.init_params(0, zero_output=False)
+        z = G.rademacher(prob.n, torch.Generator().manual_seed(0))
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        grad = torch.zeros_like(theta)
+        Lp = g.forward(theta)
+        g.loss_grad(theta, z, loss, grad)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.forward(theta, out=Lp)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t
+        t = time.perf_counter()
+        g.loss_grad(theta, z, loss, grad)
+        torch.cuda.synchronize()
+        t_lg = time.perf_counter() - t
+        gnn = dict(params=G.num_params(), edges=int(P64.L.nnz), forward_ms=round(1e3 * t_fwd, 2),
+                   loss_grad_ms=round(1e3 * t_lg, 2), loss=float(loss.item()))
+        log(f"gnn: forward {1e3 * t_fwd:.1f} ms, loss+gradient {1e3 * t_lg:.1f} ms over {gnn['edges']} edges")
+        del g, Lp, grad
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.skip_cpu:
         k64 = variants.get("fp64", {}).get("iters", 800)
@@ -358,6 +385,7 @@ def main():
                                    row_levels=finfo_c["nlevels"], supernode_levels_L=pinfo_c["nsn_levels_L"],
                                    supernode_levels_U=pinfo_c["nsn_levels_U"]),
         "variants": variants,
+        "gnn_correction": gnn,
         "kernels": {k_: dict(ms=round(v["s"] * 1e3, 4), algorithmic_GBs=round(v["gbs"], 1),
                              bytes=v["bytes"]) for k_, v in kernels.items()},
     }
