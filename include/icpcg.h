@@ -42,6 +42,11 @@
  *                            (16 or 32; default 32 below 8 columns, else 16)
  *   ICPCG_SPMV_SLOTS         entry slots per row of the plain SpMV (default 16)
  *   ICPCG_NO_ROW_GROUPS      when set, analysed matrices use the plain SpMV
+ *   ICPCG_WAIT_LIMIT_US      time limit of one device-side dependency wait
+ *                            (default 4 s); a wait that reaches it gives up,
+ *                            the kernel finishes with a NaN in that place and
+ *                            the call (or the next icpcg_sync) reports
+ *                            ICPCG_E_DEVICE
  */
 #ifndef ICPCG_H
 #define ICPCG_H

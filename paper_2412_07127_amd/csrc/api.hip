@@ -167,6 +167,10 @@ icpcg_status icpcg_create(icpcg_ctx **out, void *stream) {
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0)
     ctx->dev.wall_hz = (long long)v * 1000LL;  // attribute is in kHz
   ctx->dev.wait_ticks = ctx->dev.wall_hz * 4;  // 4 s
+  if (const char *e = std::getenv("ICPCG_WAIT_LIMIT_US")) {
+    const long long us = std::atoll(e);
+    if (us >= 0) ctx->dev.wait_ticks = ctx->dev.wall_hz / 1000000 * us;
+  }
   if (const char *e = std::getenv("ICPCG_TRSV_WAVES_PER_CU")) ctx->dev.trsv_waves_per_cu = std::atoi(e);
   if (ensure_flags(ctx) != ICPCG_OK) {
     delete ctx;

@@ -335,3 +335,24 @@ def test_pivot_breakdown_gives_up_with_status(ctx):
     A = named_matrix("kershaw")
     Lg, info = ctx.factor(to_gpu(A), max_restarts=0, raise_on_pivot=False)
     assert info["status"] == pkg._lib.E_PIVOT and info["alpha"] == 0.0
+
+
+def test_dependency_wait_limit_reports_device_error(ctx, monkeypatch):
+    """Failure handling forced from the host: a context whose dependency waits
+    may not wait at all gives up every pending wait (the kernels still finish)
+    and the solve reports ICPCG_E_DEVICE; other contexts are unaffected."""
+    prob, b = workload_problem("q1_8")
+    A = to_gpu((prob.row_ptr, prob.col, prob.val))
+    Lg, _ = ctx.factor(A)
+    P = ctx.prec(Lg, "f64")
+    monkeypatch.setenv("ICPCG_WAIT_LIMIT_US", "0")
+    ctx0 = pkg.Context()
+    monkeypatch.delenv("ICPCG_WAIT_LIMIT_US")
+    bt = torch.from_numpy(b).cuda()
+    with pytest.raises(pkg.IcpcgError) as ei:
+        ctx0.solve(A, P, bt, rtol=1e-8)
+    assert ei.value.status == pkg._lib.E_DEVICE
+    assert "time limit" in str(ei.value)
+    X, info = ctx.solve(A, P, bt, rtol=1e-8)
+    assert info[0]["status"] == 0 and info[0]["true_relres"] <= 1e-8
+    ctx0.close()
