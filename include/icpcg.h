@@ -40,6 +40,9 @@
  *                            triangular solves (default: all that fit)
  *   ICPCG_SPMVG_SLOTS        entry slots per row group of the grouped SpMV
  *                            (16 or 32; default 32 below 8 columns, else 16)
+ *   ICPCG_SPMVG_ITERS        row groups per lane group and block of the grouped
+ *                            SpMV (default 1, 1, 2, 8, 16 at 1, 2, 4, 8, 16
+ *                            columns)
  *   ICPCG_SPMV_SLOTS         entry slots per row of the plain SpMV (default 16)
  *   ICPCG_NO_ROW_GROUPS      when set, analysed matrices use the plain SpMV
  *   ICPCG_WAIT_LIMIT_US      time limit of one device-side dependency wait

@@ -204,7 +204,8 @@ int launch_grp(const int32_t *ci, const double *v, int64_t ngroups, const SpGrou
   // Short chunks keep the groups in flight on one XCD close together, so its
   // L2 serves more of the neighbouring x gathers (measured best per width);
   // the fused p^T w partials bound the block count.
-  constexpr int ITERS = R >= 16 ? 16 : R >= 8 ? 8 : R >= 4 ? 2 : 1;
+  static const int iters_env = std::getenv("ICPCG_SPMVG_ITERS") ? std::atoi(std::getenv("ICPCG_SPMVG_ITERS")) : 0;
+  const int ITERS = iters_env > 0 ? iters_env : (R >= 16 ? 16 : R >= 8 ? 8 : R >= 4 ? 2 : 1);
   int64_t nb = (ngroups + GPB * ITERS - 1) / (GPB * ITERS);
   if (partials && nb > kMaxDotBlocks) nb = kMaxDotBlocks;
   if (nb < 1) nb = 1;
