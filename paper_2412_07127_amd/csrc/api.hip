@@ -260,7 +260,7 @@ icpcg_status icpcg_factor(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *L_row_ptr
     if (restarts > 0) alpha = std::max(alpha_min, 2.0 * alpha);
     if ((st = fill_i32(fl.as<int32_t>(), 0, 1, s))) return finish(ctx, st);
     if ((st = ic0_factor_levels(L_row_ptr, L_col, L_val, a_low.as<double>(), n, perm.as<int32_t>(), hlp, alpha,
-                                fl.as<int>(), pivots.as<double>(), s, maxlen)))
+                                fl.as<int>(), pivots.as<double>(), s, maxlen, ctx->dev.num_cu)))
       return finish(ctx, st);
     int hfail = 0;
     if (hipMemcpyAsync(&hfail, fl.p, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)

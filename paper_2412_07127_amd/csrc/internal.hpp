@@ -208,7 +208,7 @@ int row_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int3
 // ------------------------------------------------------------ kernels
 int ic0_factor_levels(const int64_t *lrp, const int32_t *lci, double *lv, const double *a_lower,
                       int64_t n, const int32_t *perm, const std::vector<int32_t> &level_ptr,
-                      double alpha, int *fail_flag, double *pivots, hipStream_t s, int max_row_len);
+                      double alpha, int *fail_flag, double *pivots, hipStream_t s, int max_row_len, int num_cu);
 int ic0_max_row();
 
 // multicolour ordering (order.hip)
