@@ -75,7 +75,7 @@ struct SolveFlags {
 
 // Work buffers of a context (grow monotonically).
 struct Workspace {
-  DevBuf r, p, w, y, z, partials, cols, flags, tmp0, tmp1, tmp2, tmp3, tmp4, tmp5, agrp;
+  DevBuf r, p, w, y, z, partials, cols, flags, tmp0, tmp1;
   void *host_flags = nullptr;  // pinned SolveFlags
 };
 
