@@ -45,6 +45,10 @@
  *                            columns)
  *   ICPCG_SPMV_SLOTS         entry slots per row of the plain SpMV (default 16)
  *   ICPCG_NO_ROW_GROUPS      when set, analysed matrices use the plain SpMV
+ *   ICPCG_IC0_SYNC_FREE      when set to a nonzero integer, icpcg_factor runs
+ *                            each shift attempt as one sync-free launch
+ *                            instead of one launch per level of tril(A) (same
+ *                            bits; slower on the elasticity workloads)
  *   ICPCG_WAIT_LIMIT_US      time limit of one device-side dependency wait
  *                            (default 4 s); a wait that reaches it gives up,
  *                            the kernel finishes with a NaN in that place and
@@ -125,13 +129,17 @@ typedef struct {
 
 /* IC(0): lower L on the pattern of tril(A) with (L L^T)_ij = A_ij on that
  * pattern (Model Architecture section; zero fill). Computed in FP64 on the
- * GPU, rows scheduled by level. A pivot that is not > 0 restarts on
+ * GPU, one wave per row, one launch per level of tril(A)'s row schedule (or
+ * one sync-free launch per shift attempt, see ICPCG_IC0_SYNC_FREE); the result
+ * does not depend on the schedule. A pivot that is not > 0 restarts on
  * A + alpha diag(A) with alpha = 0, alpha_min, 2 alpha_min, 4 alpha_min, ...
  * (the paper uses IC(0) as a black box; this global shift is this library's
  * rule). Outputs L_row_ptr[n+1], L_col[nnz_lower], L_val[nnz_lower] (caller
  * buffers sized by icpcg_tril_nnz). opts and info may be NULL.
- * Errors: ICPCG_E_INVALID (malformed A, row of tril(A) longer than 4096),
- * ICPCG_E_PIVOT (every shift failed; L holds the last attempt). */
+ * Errors: ICPCG_E_INVALID (malformed A, row of tril(A) longer than 1024),
+ * ICPCG_E_PIVOT (every shift failed; L holds the last attempt, with NaN or
+ * pending entries where that attempt stopped), ICPCG_E_DEVICE (a dependency
+ * wait reached its time limit). */
 icpcg_status icpcg_factor(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *L_row_ptr,
                           int32_t *L_col, double *L_val, const icpcg_factor_opts *opts,
                           icpcg_factor_info *info);

@@ -172,6 +172,7 @@ icpcg_status icpcg_create(icpcg_ctx **out, void *stream) {
     if (us >= 0) ctx->dev.wait_ticks = ctx->dev.wall_hz / 1000000 * us;
   }
   if (const char *e = std::getenv("ICPCG_TRSV_WAVES_PER_CU")) ctx->dev.trsv_waves_per_cu = std::atoi(e);
+  if (const char *e = std::getenv("ICPCG_IC0_SYNC_FREE")) ctx->dev.ic0_sync_free = std::atoi(e) != 0;
   if (ensure_flags(ctx) != ICPCG_OK) {
     delete ctx;
     return ICPCG_E_NOMEM;
@@ -234,7 +235,7 @@ icpcg_status icpcg_factor(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *L_row_ptr
   hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, L_row_ptr + n, nnzl);
   DevBuf a_low, pivots, lens, perm, lptr, fl;
   if (a_low.reserve(nnzl * 8) || pivots.reserve(n * 8) || lens.reserve(n * 4) || perm.reserve(n * 4) ||
-      lptr.reserve((n + 1) * 4) || fl.reserve(4))
+      lptr.reserve((n + 1) * 4) || fl.reserve(12))
     return finish(ctx, ICPCG_E_NOMEM);
   if ((st = tril_copy(A->row_ptr, A->col, A->val, n, L_row_ptr, L_col, a_low.as<double>(), s))) return finish(ctx, st);
   // longest row (LDS staging limit)
@@ -249,23 +250,34 @@ icpcg_status icpcg_factor(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *L_row_ptr
   if ((st = row_levels(L_row_ptr, L_col, n, false, nullptr, perm.as<int32_t>(), lptr.as<int32_t>(), &nlev, s,
                        ctx->dev)))
     return finish(ctx, st);
-  std::vector<int32_t> hlp((size_t)nlev + 1);
-  if (hipMemcpyAsync(hlp.data(), lptr.p, (nlev + 1) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return fail(ctx, ICPCG_E_DEVICE, "factor: level copy failed");
+  const bool by_levels = !ctx->dev.ic0_sync_free;
+  std::vector<int32_t> hlp;
+  if (by_levels) {
+    hlp.resize((size_t)nlev + 1);
+    if (hipMemcpyAsync(hlp.data(), lptr.p, (nlev + 1) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(ctx, ICPCG_E_DEVICE, "factor: level copy failed");
+  }
   double alpha = 0.0;
   int restarts = 0;
   int ok = 0;
   for (restarts = 0; restarts <= max_restarts; ++restarts) {
     if (restarts > 0) alpha = std::max(alpha_min, 2.0 * alpha);
-    if ((st = fill_i32(fl.as<int32_t>(), 0, 1, s))) return finish(ctx, st);
-    if ((st = ic0_factor_levels(L_row_ptr, L_col, L_val, a_low.as<double>(), n, perm.as<int32_t>(), hlp, alpha,
-                                fl.as<int>(), pivots.as<double>(), s, maxlen, ctx->dev.num_cu)))
-      return finish(ctx, st);
-    int hfail = 0;
-    if (hipMemcpyAsync(&hfail, fl.p, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    if ((st = fill_i32(fl.as<int32_t>(), 0, 3, s))) return finish(ctx, st);  // failure flag, wait error, ticket
+    if (by_levels) {
+      st = ic0_factor_levels(L_row_ptr, L_col, L_val, a_low.as<double>(), n, perm.as<int32_t>(), hlp, alpha,
+                             fl.as<int>(), pivots.as<double>(), s, maxlen, ctx->dev);
+    } else if (!(st = fill_pending(L_val, nnzl, false, s))) {
+      st = ic0_factor_sync(L_row_ptr, L_col, L_val, a_low.as<double>(), n, perm.as<int32_t>(), alpha, fl.as<int>(),
+                           fl.as<int>() + 1, fl.as<int>() + 2, pivots.as<double>(), s, maxlen, ctx->dev);
+    }
+    if (st) return finish(ctx, st);
+    int hfl[2] = {0, 0};
+    if (hipMemcpyAsync(hfl, fl.p, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
       return fail(ctx, ICPCG_E_DEVICE, "factor: flag copy failed");
-    if (!hfail) { ok = 1; break; }
+    if (hfl[1])
+      return fail(ctx, ICPCG_E_DEVICE, "factor: a dependency wait reached its time limit");
+    if (!hfl[0]) { ok = 1; break; }
   }
   if (restarts > max_restarts) restarts = max_restarts;
   double minp = 0.0;

@@ -79,6 +79,35 @@ __device__ __forceinline__ T wait_value(const T *p, int *err, long long limit) {
   return bitcast<T>(v);
 }
 
+// Wait (one lane) until the value-as-flag FP64 entry *p no longer holds the
+// pending pattern, with exponential backoff between polls so that many
+// waiting waves do not flood the memory system. Returns false (and raises
+// err) at the time limit, or when *abandon (nullable) becomes nonzero.
+__device__ __forceinline__ bool poll_f64(const double *p, int *err, long long limit, const int *abandon) {
+  const unsigned long long *u = reinterpret_cast<const unsigned long long *>(p);
+  if (ld_agent(u) != Flag<double>::kPending) return true;
+  const long long t0 = wall_clock64();
+  int backoff = 1;
+  while (true) {
+    for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(2);
+    if (backoff < 16) backoff <<= 1;
+    if (ld_agent(u) != Flag<double>::kPending) return true;
+    if (abandon && ld_agent(abandon)) return false;
+    if (wall_clock64() - t0 > limit) {
+      __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+  }
+}
+
+// Next ticket of a one-wave work queue: lane 0 takes it with a (vector)
+// atomic and the wave shares it. Tickets taken by one wave rise.
+__device__ __forceinline__ unsigned take_ticket(unsigned *ticket) {
+  unsigned t = 0;
+  if (threadIdx.x == 0) t = atomicAdd(ticket, 1u);
+  return __shfl(t, 0, ICPCG_WAVE);
+}
+
 template <typename T>
 __device__ __forceinline__ void publish_value(T *p, T x) {
   using U = typename Flag<T>::U;

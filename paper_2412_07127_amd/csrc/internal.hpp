@@ -49,6 +49,7 @@ struct Device {
   int id = 0;
   int num_cu = 256;
   int trsv_waves_per_cu = 0;  // 0: as many as fit
+  bool ic0_sync_free = false;  // IC(0) in one sync-free launch instead of level launches
   long long wall_hz = 100000000;  // wall_clock64 rate
   long long wait_ticks = 400000000;  // device-side wait limit (4 s)
 };
@@ -206,9 +207,17 @@ int row_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int3
                const Device &dev);
 
 // ------------------------------------------------------------ kernels
+// IC(0) with one launch per level of tril(A)'s row schedule (level_ptr on the
+// host), or in one sync-free launch over the rows in level order (lv filled
+// with the pending pattern and *ticket zeroed first; err raised when a wait
+// reaches its limit).
 int ic0_factor_levels(const int64_t *lrp, const int32_t *lci, double *lv, const double *a_lower,
                       int64_t n, const int32_t *perm, const std::vector<int32_t> &level_ptr,
-                      double alpha, int *fail_flag, double *pivots, hipStream_t s, int max_row_len, int num_cu);
+                      double alpha, int *fail_flag, double *pivots, hipStream_t s, int max_row_len,
+                      const Device &dev);
+int ic0_factor_sync(const int64_t *lrp, const int32_t *lci, double *lv, const double *a_lower, int64_t n,
+                    const int32_t *order, double alpha, int *fail_flag, int *err, int *ticket, double *pivots,
+                    hipStream_t s, int max_row_len, const Device &dev);
 int ic0_max_row();
 
 // multicolour ordering (order.hip)
