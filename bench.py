@@ -107,36 +107,55 @@ def recorded_traffic(kernel):
 
 def time_kernels(ctx, M, P, R, reps, torch):
     """Average duration of one SpMV (the row-group kernel the solver uses) and
-    one forward/backward solve launch at block width R, with events on the
-    stream the library launches on."""
+    one forward and one backward solve launch at block width R, with events on
+    the stream the library launches on. The three are launched in a PCG step's
+    order (SpMV, forward, backward) and timed each time, so every launch meets
+    the cache state the step leaves (the SpMV streams A and x through the
+    caches between two solves)."""
     n = M.n
     X = torch.randn(n, R, dtype=torch.float64, device="cuda")
     W = torch.empty_like(X)
     Rf = torch.randn(n, R, dtype=torch.float64, device="cuda")
     Yf = P.trsv(Rf)
-    out = {}
     s = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
 
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        tot = 0.0
-        for _ in range(reps):
-            e0.record(s)
-            fn()
-            e1.record(s)
-            e1.synchronize()
-            tot += e0.elapsed_time(e1)
-        return tot / reps * 1e-3
+    # the trsv entry point fills the output with the pending pattern first; time
+    # the fill alone and subtract it so the figure is the solve kernel's
+    Yf.fill_(float("nan"))
+    torch.cuda.synchronize()
+    fill = 0.0
+    for _ in range(reps):
+        e0, e1 = ev(), ev()
+        e0.record(s)
+        Yf.fill_(float("nan"))
+        e1.record(s)
+        e1.synchronize()
+        fill += e0.elapsed_time(e1)
+    fill = fill / reps * 1e-3
 
-    out["spmv"] = timed(lambda: M.spmv(X, out=W))
-    # the trsv entry point fills the output with the pending pattern first; time the
-    # fill alone and subtract it so the figure is the solve kernel's
-    fill_lo = timed(lambda: Yf.fill_(float("nan")))
-    out["trsv_L"] = max(1e-9, timed(lambda: P.trsv(Rf)) - fill_lo)
-    out["trsv_U"] = max(1e-9, timed(lambda: P.trsv(Yf, transpose=True)) - fill_lo)
-    return out
+    def step():
+        M.spmv(X, out=W)
+        Y = P.trsv(Rf)
+        P.trsv(Y, transpose=True)
+
+    step()
+    torch.cuda.synchronize()
+    tot = [0.0, 0.0, 0.0]
+    for _ in range(reps):
+        e = [ev() for _ in range(4)]
+        e[0].record(s)
+        M.spmv(X, out=W)
+        e[1].record(s)
+        Y = P.trsv(Rf)
+        e[2].record(s)
+        P.trsv(Y, transpose=True)
+        e[3].record(s)
+        e[3].synchronize()
+        for k in range(3):
+            tot[k] += e[k].elapsed_time(e[k + 1])
+    ms = [t / reps * 1e-3 for t in tot]
+    return {"spmv": ms[0], "trsv_L": max(1e-9, ms[1] - fill), "trsv_U": max(1e-9, ms[2] - fill)}
 
 
 def cpu_baseline(prob, b, k_target, iters=8):
@@ -239,12 +258,13 @@ def main():
                           "copy_bytes_each_way": src.numel() * 8}), flush=True)
         return
 
-    def solve_in(order, Mx, Px, rhs):
+    def solve_in(order, Mx, Px, rhs, graph=False):
         """One solve of the original system: in the multicolour order the right-
-        hand sides are permuted in and the solution back (inside the timing)."""
+        hand sides are permuted in and the solution back (inside the timing).
+        graph: the steps between two convergence polls replay a captured hipGraph."""
         if order == "natural":
-            return ctx.solve(Mx, Px, rhs, rtol=args.rtol)
-        Xp, info = ctx.solve(Mx, Px, ctx.permute_rows(perm, rhs), rtol=args.rtol)
+            return ctx.solve(Mx, Px, rhs, rtol=args.rtol, use_graph=graph)
+        Xp, info = ctx.solve(Mx, Px, ctx.permute_rows(perm, rhs), rtol=args.rtol, use_graph=graph)
         return ctx.permute_rows(perm, Xp, inverse=True), info
 
     def run_single(order, Mx, Px, name):
@@ -273,12 +293,12 @@ def main():
     def multi(order, Mx, Px, name, steps, warmup):
         ctx.autotune(Mx, Px, args.nrhs)  # the width choice is setup, outside the timing
         for _ in range(warmup):
-            solve_in(order, Mx, Px, Bt)
+            solve_in(order, Mx, Px, Bt, graph=True)
         torch.cuda.synchronize()
         t = time.perf_counter()
         infos = None
         for _ in range(steps):
-            X, infos = solve_in(order, Mx, Px, Bt)
+            X, infos = solve_in(order, Mx, Px, Bt, graph=True)
         torch.cuda.synchronize()
         total = time.perf_counter() - t
         step_s = total / steps
@@ -370,8 +390,8 @@ def main():
         "config": {
             "workload": (f"Q1 elasticity {E}^3 elements, {n} DOF, nnz {nnzA}, sigma={sigma}; "
                          f"{args.nrhs} load cases per step; IC(0) FP64 on GPU (natural order), factor applied "
-                         f"in FP32; rtol {args.rtol} (true residual)"),
-            "nrhs": args.nrhs, "block_width": R, "n": n, "nnz_A": nnzA, "nnz_L": nnzL,
+                         f"in FP32; rtol {args.rtol} (true residual); steps replayed as a captured hipGraph"),
+            "nrhs": args.nrhs, "block_width": R, "n": n, "nnz_A": nnzA, "nnz_L": nnzL, "hip_graph": True,
         },
         "roofline": roof,
         "cpu_baseline": cpu,
