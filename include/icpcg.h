@@ -124,14 +124,16 @@ typedef struct {
   double alpha;        /* shift used: factor of A + alpha diag(A) */
   int restarts;        /* number of shifted restarts */
   double min_pivot;    /* smallest squared pivot of the successful attempt */
-  int64_t nlevels;     /* level count of the row schedule of tril(A) */
+  int64_t nlevels;     /* steps of the row schedule of tril(A): supernode level
+                          x 3 + position in the supernode (empty steps included) */
 } icpcg_factor_info;
 
 /* IC(0): lower L on the pattern of tril(A) with (L L^T)_ij = A_ij on that
  * pattern (Model Architecture section; zero fill). Computed in FP64 on the
- * GPU, one wave per row, one launch per level of tril(A)'s row schedule (or
- * one sync-free launch per shift attempt, see ICPCG_IC0_SYNC_FREE); the result
- * does not depend on the schedule. A pivot that is not > 0 restarts on
+ * GPU, one wave per row, one launch per step of tril(A)'s row schedule (rows
+ * ordered by the level of their supernode, then their position in it), or one
+ * sync-free launch per shift attempt (see ICPCG_IC0_SYNC_FREE); the result does
+ * not depend on the schedule. A pivot that is not > 0 restarts on
  * A + alpha diag(A) with alpha = 0, alpha_min, 2 alpha_min, 4 alpha_min, ...
  * (the paper uses IC(0) as a black box; this global shift is this library's
  * rule). Outputs L_row_ptr[n+1], L_col[nnz_lower], L_val[nnz_lower] (caller

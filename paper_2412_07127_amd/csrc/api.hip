@@ -235,7 +235,7 @@ icpcg_status icpcg_factor(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *L_row_ptr
   hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, L_row_ptr + n, nnzl);
   DevBuf a_low, pivots, lens, perm, lptr, fl;
   if (a_low.reserve(nnzl * 8) || pivots.reserve(n * 8) || lens.reserve(n * 4) || perm.reserve(n * 4) ||
-      lptr.reserve((n + 1) * 4) || fl.reserve(12))
+      lptr.reserve((kSupernodeMax * n + 1) * 4) || fl.reserve(12))
     return finish(ctx, ICPCG_E_NOMEM);
   if ((st = tril_copy(A->row_ptr, A->col, A->val, n, L_row_ptr, L_col, a_low.as<double>(), s))) return finish(ctx, st);
   // longest row (LDS staging limit)
@@ -245,10 +245,9 @@ icpcg_status icpcg_factor(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *L_row_ptr
   if (maxlen > ic0_max_row())
     return fail(ctx, ICPCG_E_INVALID, "factor: a row of tril(A) has " + std::to_string(maxlen) +
                                           " entries (limit " + std::to_string(ic0_max_row()) + ")");
-  // row levels of tril(A)
+  // row schedule of tril(A), from its supernode levels
   int64_t nlev = 0;
-  if ((st = row_levels(L_row_ptr, L_col, n, false, nullptr, perm.as<int32_t>(), lptr.as<int32_t>(), &nlev, s,
-                       ctx->dev)))
+  if ((st = supernode_row_order(L_row_ptr, L_col, n, perm.as<int32_t>(), lptr.as<int32_t>(), &nlev, s, ctx->dev)))
     return finish(ctx, st);
   const bool by_levels = !ctx->dev.ic0_sync_free;
   std::vector<int32_t> hlp;

@@ -202,6 +202,11 @@ struct SpGroup {
 // and their SpGroup records (rows must have fewer than 2^28 entries).
 int build_row_groups(const int64_t *rp, const int32_t *ci, int64_t n, int gmax, DevBuf &gptr, DevBuf &grec,
                      int64_t *ngroups, hipStream_t s);
+// Row schedule of a lower pattern from its supernode levels (key = supernode
+// level * kSupernodeMax + position in the supernode); key_ptr needs room for
+// kSupernodeMax * n + 1 entries.
+int supernode_row_order(const int64_t *rp, const int32_t *ci, int64_t n, int32_t *perm, int32_t *key_ptr,
+                        int64_t *nkeys_host, hipStream_t s, const Device &dev);
 int row_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int32_t *level,
                int32_t *perm, int32_t *level_ptr, int64_t *nlev_host, hipStream_t s,
                const Device &dev);

@@ -580,6 +580,46 @@ int build_schedule(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, 
   return ICPCG_OK;
 }
 
+// Row schedule of a lower pattern derived from its supernode levels: row r of
+// supernode S (position p in it) gets the key level(S) * kSupernodeMax + p.
+// Every dependency of r lies in a supernode of a lower level or earlier in S,
+// so ordering rows by key is a valid schedule; it has about as many steps as
+// the row levels on node-structured matrices (3-DOF nodes) but the analysis
+// walks supernodes, not rows. Outputs the rows sorted by (key, row), the key
+// pointer array (kSupernodeMax * n + 1 entries at most) and its length.
+__global__ void k_sn_row_keys(const int32_t *__restrict__ sn_of_row, const int32_t *__restrict__ sn_ptr,
+                              const int32_t *__restrict__ level, int64_t n, int32_t *__restrict__ key) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t sn = sn_of_row[r];
+    key[r] = level[sn] * kSupernodeMax + (int32_t)(r - sn_ptr[sn]);
+  }
+}
+
+int supernode_row_order(const int64_t *rp, const int32_t *ci, int64_t n, int32_t *perm, int32_t *key_ptr,
+                        int64_t *nkeys_host, hipStream_t s, const Device &dev) {
+  int st;
+  DevBuf begin, sn_of_row, sn_ptr, level, err, key;
+  if (begin.reserve(n * 4) || sn_of_row.reserve(n * 4) || err.reserve(4) || key.reserve(n * 4))
+    return ICPCG_E_NOMEM;
+  hipLaunchKernelGGL(k_sn_begin<false>, dim3(grid_rows(n, 4)), dim3(kBlock), 0, s, rp, ci, n, begin.as<int32_t>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  int64_t nsn = 0;
+  if ((st = runs_to_pieces(begin.as<int32_t>(), n, kSupernodeMax, sn_ptr, sn_of_row.as<int32_t>(), &nsn, s)))
+    return st;
+  if (level.reserve(nsn * 4)) return ICPCG_E_NOMEM;
+  if ((st = fill_i32(level.as<int32_t>(), -1, nsn, s)) || (st = fill_i32(err.as<int32_t>(), 0, 1, s))) return st;
+  auto k = k_levels<false, false>;
+  const int grid = resident_grid(k, kBlock, dev, nsn);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, s, rp, ci, (int64_t)nsn, sn_ptr.as<int32_t>(),
+                     sn_of_row.as<int32_t>(), level.as<int>(), err.as<int>(), dev.wait_ticks);
+  ICPCG_HIP_TRY(hipGetLastError());
+  if ((st = check_err_flag(err, s, "supernode level analysis"))) return st;
+  hipLaunchKernelGGL(k_sn_row_keys, dim3(grid_rows(n, kBlock)), dim3(kBlock), 0, s, sn_of_row.as<int32_t>(),
+                     sn_ptr.as<int32_t>(), level.as<int32_t>(), n, key.as<int32_t>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  return sort_by_level(key.as<int32_t>(), n, perm, key_ptr, nkeys_host, s);
+}
+
 // Row level sets (bit-exact integers): level, rows sorted by (level, row) and
 // the level pointer array.
 int row_levels(const int64_t *rp, const int32_t *ci, int64_t n, bool upper, int32_t *level, int32_t *perm,
