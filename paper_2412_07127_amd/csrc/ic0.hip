@@ -406,15 +406,52 @@ int ic0_factor_levels(const int64_t *lrp, const int32_t *lci, double *lv, const 
     per_cu = 1;
   }
   const int64_t staged_round = (int64_t)per_cu * dev.num_cu;
-  for (size_t l = 0; l + 1 < level_ptr.size(); ++l) {
-    const int32_t b = level_ptr[l], e = level_ptr[l + 1];
-    if (e <= b) continue;
-    const bool stage = (int64_t)(e - b) <= staged_round;
-    hipLaunchKernelGGL(k_ic0_rows, dim3((unsigned)(e - b)), dim3(64), stage ? lds_staged : lds_plain, s, perm + b, lrp,
-                       lci, lv, a_low, alpha, fail, pivots, max_row_len, stage ? kMatchCap : 0);
+  // A failed attempt's remaining launches return at once, but launching them
+  // still costs time: every kBatch levels the failure flag is copied to pinned
+  // memory behind an event, and before the next batch is queued the host looks
+  // at the previous batch's copy (one batch stays queued, so the GPU does not
+  // wait for the host) and stops queueing once the attempt has failed.
+  constexpr size_t kBatch = 256;
+  int *hflag = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int st = ICPCG_OK;
+  if (hipHostMalloc(reinterpret_cast<void **>(&hflag), 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    st = ICPCG_E_DEVICE;
   }
-  ICPCG_HIP_TRY(hipGetLastError());
-  return ICPCG_OK;
+  const size_t nlev = level_ptr.empty() ? 0 : level_ptr.size() - 1;
+  for (size_t l0 = 0, bt = 0; st == ICPCG_OK && l0 < nlev; l0 += kBatch, ++bt) {
+    for (size_t l = l0; l < std::min(nlev, l0 + kBatch); ++l) {
+      const int32_t b = level_ptr[l], e = level_ptr[l + 1];
+      if (e <= b) continue;
+      const bool stage = (int64_t)(e - b) <= staged_round;
+      hipLaunchKernelGGL(k_ic0_rows, dim3((unsigned)(e - b)), dim3(64), stage ? lds_staged : lds_plain, s, perm + b,
+                         lrp, lci, lv, a_low, alpha, fail, pivots, max_row_len, stage ? kMatchCap : 0);
+    }
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(hflag + (bt & 1), fail, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(ev[bt & 1], s) != hipSuccess) {
+      st = ICPCG_E_DEVICE;
+      break;
+    }
+    if (bt > 0) {
+      if (hipEventSynchronize(ev[(bt - 1) & 1]) != hipSuccess) {
+        st = ICPCG_E_DEVICE;
+        break;
+      }
+      if (hflag[(bt - 1) & 1]) break;  // the caller reads the flag after the stream drains
+    }
+  }
+  if (st) set_error("factor: level launch or failure-flag copy failed");
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (hflag) {
+    (void)hipStreamSynchronize(s);  // the last copy into the pinned flags has landed
+    (void)hipHostFree(hflag);
+  }
+  return st;
 }
 
 int ic0_factor_sync(const int64_t *lrp, const int32_t *lci, double *lv, const double *a_low, int64_t n,
