@@ -104,7 +104,7 @@ template <int SLOTS> struct GrpDepth {
 };
 
 template <int R, int SLOTS, bool DOT, int CPL, int QD = GrpDepth<SLOTS>::v>
-__global__ __launch_bounds__(kBlock) void k_spmv_grp(const int32_t *__restrict__ ci, const double *__restrict__ v,
+__global__ __launch_bounds__(kBlock, 3) void k_spmv_grp(const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                      int64_t ngroups, const SpGroup *__restrict__ grec,
                                                      const double *__restrict__ x, double *__restrict__ y,
                                                      int64_t chunk, double *partials,
@@ -117,6 +117,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_grp(const int32_t *__restrict__
   constexpr int GPB = kBlock / GROUP;
   const int t = threadIdx.x;
   const int g = t / GROUP, lg = t % GROUP, slot = lg / LPR, c0 = (lg % LPR) * CPL;
+  __shared__ double pdiag[DOT ? GPB * GMAX * R : 1];  // per group: p of its rows, [u][column]
+  double *pd = pdiag + (DOT ? g * GMAX * R : 0);
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int64_t g0 = lb * chunk;
   const int64_t g1 = g0 + chunk < ngroups ? g0 + chunk : ngroups;
@@ -147,6 +149,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_grp(const int32_t *__restrict__
     for (int u = 0; u < GMAX; ++u)
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) acc[u][cc] = 0.0;
+    // for the fused p^T w: the group's rows are among its shared columns, so
+    // p of row r0 + u is the x gathered for that column; the lane that
+    // gathers it leaves it in the group's LDS table (read back after the
+    // butterfly by the lanes that write w; one wave, so LDS order suffices)
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
       const int64_t q = slot + k * SLOTS;
@@ -159,10 +165,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_grp(const int32_t *__restrict__
         for (int u = 0; u < GMAX; ++u)
 #pragma unroll
           for (int cc = 0; cc < CPL; ++cc) acc[u][cc] += vv[k][u] * xv[cc];
+        if (DOT && jj[k] >= r0 && jj[k] < r0 + sz) {
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc) pd[(jj[k] - r0) * R + c0 + cc] = xv[cc];
+        }
       }
     }
     for (int64_t q = slot + QD * SLOTS; q < m; q += SLOTS) {
-      const double *xr = x + (int64_t)ci[base + q] * R + c0;
+      const int32_t j = ci[base + q];
+      const double *xr = x + (int64_t)j * R + c0;
       double xv[CPL];
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) xv[cc] = xr[cc];
@@ -171,6 +182,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_grp(const int32_t *__restrict__
         const double vq = u < sz ? v[base + u * m + q] : 0.0;
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) acc[u][cc] += vq * xv[cc];
+      }
+      if (DOT && j >= r0 && j < r0 + sz) {
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) pd[(j - r0) * R + c0 + cc] = xv[cc];
       }
     }
 #pragma unroll
@@ -185,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_grp(const int32_t *__restrict__
 #pragma unroll
           for (int cc = 0; cc < CPL; ++cc) {
             y[row * R + c0 + cc] = acc[u][cc];
-            if (DOT) dot[cc] += x[row * R + c0 + cc] * acc[u][cc];
+            if (DOT) dot[cc] += pd[u * R + c0 + cc] * acc[u][cc];
           }
         }
       }
