@@ -1,6 +1,8 @@
 // CSR sparse matrix times an R-column block, FP64 (w = A p of supplementary
 // Algorithm 1), with an optional fused p^T w reduction (deterministic block
-// partials; a one-block finalize kernel computes alpha = r^T z / p^T w).
+// partials; a one-block finalize kernel computes alpha = r^T z / p^T w). The
+// fused dot takes p of each row from the x gathered for its diagonal column
+// (passed through LDS), so it adds no load after the row's sum.
 //
 // Mapping (wave64): a group of SLOTS * R / CPL lanes owns one row (one row
 // group in the grouped kernel); a lane owns CPL consecutive columns (min(R, 4)
@@ -45,6 +47,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t *__restrict__ rp,
   const int t = threadIdx.x;
   const int g = t / GROUP, lg = t % GROUP, slot = lg / LPR, c0 = (lg % LPR) * CPL;
   (void)t;
+  // for the fused p^T w: p of the row is the x gathered for its diagonal (every
+  // row stores it); the lane that gathers it leaves it in the group's LDS slot
+  __shared__ double pdiag[DOT ? GPB * R : 1];
+  double *pd = pdiag + (DOT ? g * R : 0);
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int64_t r0 = lb * chunk;
   const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
@@ -69,15 +75,30 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t *__restrict__ rp,
       const int64_t q = s + slot + k * SLOTS;
       if (q < e) {
         const double *xr = x + (int64_t)jj[k] * R + c0;
+        double xv[CPL];
 #pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) acc[cc] += vv[k] * xr[cc];
+        for (int cc = 0; cc < CPL; ++cc) xv[cc] = xr[cc];
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) acc[cc] += vv[k] * xv[cc];
+        if (DOT && jj[k] == row) {
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc) pd[c0 + cc] = xv[cc];
+        }
       }
     }
     for (int64_t q = s + slot + QD * SLOTS; q < e; q += SLOTS) {
-      const double *xr = x + (int64_t)ci[q] * R + c0;
+      const int32_t j = ci[q];
+      const double *xr = x + (int64_t)j * R + c0;
       const double vq = v[q];
+      double xv[CPL];
 #pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) acc[cc] += vq * xr[cc];
+      for (int cc = 0; cc < CPL; ++cc) xv[cc] = xr[cc];
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) acc[cc] += vq * xv[cc];
+      if (DOT && j == row) {
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) pd[c0 + cc] = xv[cc];
+      }
     }
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) acc[cc] = xor_sum_bits<Log2<LPR>::v, Log2<GROUP>::v>(acc[cc]);
@@ -85,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t *__restrict__ rp,
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) {
         y[row * R + c0 + cc] = acc[cc];
-        if (DOT) dot[cc] += x[row * R + c0 + cc] * acc[cc];
+        if (DOT) dot[cc] += pd[c0 + cc] * acc[cc];
       }
     }
   }
