@@ -347,6 +347,21 @@ icpcg_status icpcg_solve_mat(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_pre
 icpcg_status icpcg_color_order(icpcg_ctx *ctx, const icpcg_csr *A, uint64_t seed, int32_t *perm,
                                int32_t *ncolours);
 
+/* Block multicolour order (the block variant of the ordering above): the
+ * caller partitions the rows into blocks (block: device, n int32, values in
+ * [0, nblocks); for instance blocks of mesh nodes, a node's rows in one
+ * block). Blocks coupled by a stored entry of A are neighbours; block b takes
+ * the smallest colour not used by its neighbours of lower id (sequential first
+ * fit in id order; on a grid of blocks numbered like its nodes this gives the
+ * 8-colour parity pattern), and perm (device, n int32, new row -> old row)
+ * lists the rows by (colour of their block, block, row). Blocks keep the
+ * locality of the original order inside them while the colours cut the
+ * dependency chains of the triangular solves; *ncolours (host) receives the
+ * colour count. Synchronizes the stream. Errors: ICPCG_E_INVALID (malformed
+ * A, a block id out of range, more than 256 colours), ICPCG_E_NOMEM. */
+icpcg_status icpcg_block_color_order(icpcg_ctx *ctx, const icpcg_csr *A, const int32_t *block,
+                                     int32_t nblocks, int32_t *perm, int32_t *ncolours);
+
 /* B = P A P^T (entry (i, j) = A[perm[i], perm[j]]) into caller-owned device
  * buffers (row_ptr n + 1, col and val nnz(A)), rows with ascending columns.
  * Synchronizes the stream. Errors: ICPCG_E_INVALID (perm not a permutation,

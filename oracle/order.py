@@ -17,7 +17,10 @@ computes, in plain numpy and Python loops (small inputs only):
   * order: nodes sorted by (colour, node id), each node's rows kept together
     and in order; perm[new row] = old row;
   * the permuted matrix P A P^T: entry (i, j) = A[perm[i], perm[j]], rows
-    with ascending columns.
+    with ascending columns;
+  * block multicolour: for a caller's partition of the rows into blocks, the
+    block graph (b ~ c when a row of b stores a column of c) coloured first
+    fit in block id order, rows sorted by (colour of their block, block, row).
 
 Only the tests use it; it shares no code with the GPU library.
 """
@@ -111,3 +114,44 @@ def permute(A, perm):
         vals.append(v[rp[o]:rp[o + 1]][s])
         out_rp[i + 1] = out_rp[i] + len(c)
     return out_rp, np.concatenate(cols).astype(np.int32), np.concatenate(vals).astype(np.float64)
+
+
+def block_graph(A, blk, nblk):
+    """Adjacency lists of the block graph of a row partition blk: b ~ c when a
+    row of block b stores a column of block c (b != c); sorted."""
+    rp, ci, _ = A
+    n = len(rp) - 1
+    adj = [set() for _ in range(nblk)]
+    for i in range(n):
+        b = int(blk[i])
+        for c in blk[ci[rp[i]:rp[i + 1]]]:
+            if int(c) != b:
+                adj[b].add(int(c))
+    return [np.array(sorted(s), np.int64) for s in adj]
+
+
+def first_fit_in_id_order(adj):
+    """Sequential greedy colouring: vertex 0, 1, 2, ... each takes the smallest
+    colour not used by its already coloured (lower id) neighbours."""
+    col = np.full(len(adj), -1, np.int64)
+    for v in range(len(adj)):
+        used = {int(col[u]) for u in adj[v] if u < v}
+        c = 0
+        while c in used:
+            c += 1
+        col[v] = c
+    return col
+
+
+def block_color_order(A, blk, nblk=None):
+    """Block multicolour order of a row partition (blk[i] = block of row i):
+    the block graph coloured first-fit in block id order, rows sorted by
+    (colour of their block, block, row). Returns (perm int32: new row -> old
+    row, block colours, number of colours)."""
+    blk = np.asarray(blk, np.int64)
+    nblk = int(blk.max()) + 1 if nblk is None else int(nblk)
+    adj = block_graph(A, blk, nblk)
+    col = first_fit_in_id_order(adj)
+    rows = np.arange(len(blk))
+    perm = np.lexsort((rows, blk, col[blk])).astype(np.int32)  # last key is the primary one
+    return perm, col, int(col.max()) + 1 if len(col) else 0

@@ -99,6 +99,7 @@ def load():
         "icpcg_solve_mat": ([P, P, P, P, P, i64, C.POINTER(SolveOpts), C.POINTER(ColInfo)], st),
         "icpcg_autotune": ([P, P, P, i64, C.POINTER(TuneInfo)], st),
         "icpcg_color_order": ([P, C.POINTER(Csr), C.c_uint64, P, C.POINTER(C.c_int32)], st),
+        "icpcg_block_color_order": ([P, C.POINTER(Csr), P, C.c_int32, P, C.POINTER(C.c_int32)], st),
         "icpcg_permute_matrix": ([P, C.POINTER(Csr), P, P, P, P], st),
         "icpcg_permute_rows": ([P, P, i64, i64, P, P, st], st),
         "icpcg_gnn_num_params": ([], i64),

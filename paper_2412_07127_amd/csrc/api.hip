@@ -982,6 +982,18 @@ extern "C" icpcg_status icpcg_color_order(icpcg_ctx *ctx, const icpcg_csr *A, ui
   return finish(ctx, color_order(A->row_ptr, A->col, A->n, seed, perm, ncolours, ctx->stream));
 }
 
+extern "C" icpcg_status icpcg_block_color_order(icpcg_ctx *ctx, const icpcg_csr *A, const int32_t *block,
+                                                int32_t nblocks, int32_t *perm, int32_t *ncolours) {
+  if (!ctx || !valid_csr_args(A) || !ncolours || (A->n > 0 && (!perm || !block || nblocks < 1)) ||
+      A->nnz >= (int64_t{1} << 32))
+    return fail(ctx, ICPCG_E_INVALID, "block_color_order: bad arguments");
+  *ncolours = 0;
+  if (A->n == 0) return ICPCG_OK;
+  int st = check_matrix(ctx, A, 0);
+  if (st) return finish(ctx, st);
+  return finish(ctx, block_color_order(A->row_ptr, A->col, A->n, A->nnz, block, nblocks, perm, ncolours, ctx->stream));
+}
+
 extern "C" icpcg_status icpcg_permute_matrix(icpcg_ctx *ctx, const icpcg_csr *A, const int32_t *perm,
                                              int64_t *row_ptr, int32_t *col, double *val) {
   if (!ctx || !valid_csr_args(A) || (A->n > 0 && (!perm || !row_ptr || !col || !val)) || A->nnz >= (int64_t{1} << 32))

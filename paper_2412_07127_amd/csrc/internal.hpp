@@ -228,6 +228,8 @@ int ic0_max_row();
 // multicolour ordering (order.hip)
 int color_order(const int64_t *rp, const int32_t *ci, int64_t n, uint64_t seed, int32_t *perm, int32_t *ncolours,
                 hipStream_t s);
+int block_color_order(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nnz, const int32_t *blk, int32_t nblk,
+                      int32_t *perm, int32_t *ncolours, hipStream_t s);
 int permute_matrix(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, int64_t nnz, const int32_t *perm,
                    int64_t *orp, int32_t *oci, double *ov, hipStream_t s);
 int permute_rows(const int32_t *perm, int64_t n, int64_t R, const double *x, double *y, bool inverse, hipStream_t s);

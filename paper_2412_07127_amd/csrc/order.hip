@@ -7,6 +7,8 @@
 // Jones-Plassmann rounds compute exactly that colouring: a node is decided
 // in the round after all of its higher-key neighbours are. The order sorts
 // nodes by (colour, id) and keeps each node's rows together.
+#include <string>
+
 #include "internal.hpp"
 
 namespace icpcg {
@@ -33,11 +35,13 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-__global__ void k_node_setup(const int32_t *__restrict__ gptr, int64_t nn, uint64_t seed, int32_t *__restrict__ node_of,
-                             uint64_t *__restrict__ prio, int32_t *__restrict__ colour) {
+// Priorities: SplitMix64(seed + v), or (by_id) the reversed id, so that JP
+// rounds compute sequential first fit in increasing id order.
+__global__ void k_node_setup(const int32_t *__restrict__ gptr, int64_t nn, uint64_t seed, bool by_id,
+                             int32_t *__restrict__ node_of, uint64_t *__restrict__ prio, int32_t *__restrict__ colour) {
   for (int64_t v = gtid(); v < nn; v += gstride()) {
     for (int32_t r = gptr[v]; r < gptr[v + 1]; ++r) node_of[r] = (int32_t)v;
-    prio[v] = splitmix64(seed + (uint64_t)v);
+    prio[v] = by_id ? ~(uint64_t)v : splitmix64(seed + (uint64_t)v);
     colour[v] = -1;
   }
 }
@@ -160,6 +164,37 @@ __global__ void k_permute_rows(const int32_t *__restrict__ perm, int64_t n, int6
   }
 }
 
+// Block colouring: every entry (i, j) of A gives the pair (block of i, block
+// of j); sorted by the first, the second ones are each block's neighbour list
+// (repeats and the block itself included: the colouring round skips both).
+__global__ void k_entry_blocks(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci, int64_t n,
+                               const int32_t *__restrict__ blk, uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const uint32_t a = (uint32_t)blk[i];
+    for (int64_t t = rp[i]; t < rp[i + 1]; ++t) {
+      key[t] = a;
+      val[t] = (uint32_t)blk[ci[t]];
+    }
+  }
+}
+
+__global__ void k_block_len(const int64_t *__restrict__ rp, int64_t n, const int32_t *__restrict__ blk, int32_t nblk,
+                            unsigned long long *__restrict__ len, int *bad) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const int32_t b = blk[i];
+    if (b < 0 || b >= nblk) {
+      atomicOr(bad, 1);
+      continue;
+    }
+    atomicAdd(&len[b], (unsigned long long)(rp[i + 1] - rp[i]));
+  }
+}
+
+__global__ void k_row_colour_keys(const uint32_t *__restrict__ rows, const int32_t *__restrict__ blk,
+                                  const int32_t *__restrict__ colour, int64_t n, uint32_t *__restrict__ key) {
+  for (int64_t p = gtid(); p < n; p += gstride()) key[p] = (uint32_t)colour[blk[rows[p]]];
+}
+
 __global__ void k_set_at(int64_t *p, int64_t i, int64_t v) { p[i] = v; }
 
 int bits_for(int64_t maxval) {
@@ -176,31 +211,32 @@ int read_int(const int *dev, hipStream_t s, int *host) {
 
 }  // namespace
 
-int color_order(const int64_t *rp, const int32_t *ci, int64_t n, uint64_t seed, int32_t *perm, int32_t *ncolours,
-                hipStream_t s) {
-  DevBuf gptr, grec;
-  int64_t nn = 0;
-  int st = build_row_groups(rp, ci, n, kSupernodeMax, gptr, grec, &nn, s);
-  if (st) return st;
-  DevBuf node_of, prio, ca, cb, flags;
-  if (node_of.reserve(n * 4) || prio.reserve(nn * 8) || ca.reserve(nn * 4) || cb.reserve(nn * 4) ||
+// Jones-Plassmann colouring of nn nodes: node v's neighbours are the nodes
+// (node_of) of the columns of row gptr[v] of (rp, ci). On return *colours
+// points at ca or cb and *maxc is the largest colour.
+int jp_colour(const int64_t *rp, const int32_t *ci, const int32_t *gptr, int64_t nrows, int64_t nn, uint64_t seed,
+              bool by_id, DevBuf &node_of, DevBuf &ca, DevBuf &cb, int32_t **colours, int32_t *maxc,
+              const char *what, hipStream_t s) {
+  DevBuf prio, flags;
+  if (node_of.reserve(nrows * 4) || prio.reserve(nn * 8) || ca.reserve(nn * 4) || cb.reserve(nn * 4) ||
       flags.reserve(16))
     return ICPCG_E_NOMEM;
-  hipLaunchKernelGGL(k_node_setup, dim3(grid_for(nn)), dim3(kB), 0, s, gptr.as<int32_t>(), nn, seed,
+  hipLaunchKernelGGL(k_node_setup, dim3(grid_for(nn)), dim3(kB), 0, s, gptr, nn, seed, by_id,
                      node_of.as<int32_t>(), prio.as<uint64_t>(), ca.as<int32_t>());
   ICPCG_HIP_TRY(hipGetLastError());
   int *left = flags.as<int>(), *over = left + 1;
   ICPCG_HIP_TRY(hipMemsetAsync(over, 0, sizeof(int), s));
   int32_t *cin = ca.as<int32_t>(), *cout = cb.as<int32_t>();
+  int st;
   // every round decides at least the undecided node of highest key
   for (int64_t round = 0;; ++round) {
     if (round > nn) {
-      set_error("color_order: colouring did not finish");
+      set_error(std::string(what) + ": colouring did not finish");
       return ICPCG_E_DEVICE;
     }
     ICPCG_HIP_TRY(hipMemsetAsync(left, 0, sizeof(int), s));
-    hipLaunchKernelGGL(k_jp_round, dim3(grid_for(nn)), dim3(kB), 0, s, rp, ci, gptr.as<int32_t>(),
-                       node_of.as<int32_t>(), prio.as<uint64_t>(), nn, cin, cout, left, over);
+    hipLaunchKernelGGL(k_jp_round, dim3(grid_for(nn)), dim3(kB), 0, s, rp, ci, gptr, node_of.as<int32_t>(),
+                       prio.as<uint64_t>(), nn, cin, cout, left, over);
     ICPCG_HIP_TRY(hipGetLastError());
     std::swap(cin, cout);
     int h = 0;
@@ -210,11 +246,25 @@ int color_order(const int64_t *rp, const int32_t *ci, int64_t n, uint64_t seed, 
   int ov = 0;
   if ((st = read_int(over, s, &ov))) return st;
   if (ov) {
-    set_error("color_order: the node graph needs more than 256 colours");
+    set_error(std::string(what) + ": the graph needs more than 256 colours");
     return ICPCG_E_INVALID;
   }
-  int32_t maxc = 0;
-  if ((st = reduce_max_i32(cin, nn, s, &maxc))) return st;
+  if ((st = reduce_max_i32(cin, nn, s, maxc))) return st;
+  *colours = cin;
+  return ICPCG_OK;
+}
+
+int color_order(const int64_t *rp, const int32_t *ci, int64_t n, uint64_t seed, int32_t *perm, int32_t *ncolours,
+                hipStream_t s) {
+  DevBuf gptr, grec;
+  int64_t nn = 0;
+  int st = build_row_groups(rp, ci, n, kSupernodeMax, gptr, grec, &nn, s);
+  if (st) return st;
+  DevBuf node_of, ca, cb;
+  int32_t *cin = nullptr, maxc = 0;
+  if ((st = jp_colour(rp, ci, gptr.as<int32_t>(), n, nn, seed, false, node_of, ca, cb, &cin, &maxc, "color_order",
+                      s)))
+    return st;
   *ncolours = maxc + 1;
   // nodes by (colour, id): a stable sort of the ids on the colour
   DevBuf ids, okeys, order, sz, start;
@@ -233,6 +283,72 @@ int color_order(const int64_t *rp, const int32_t *ci, int64_t n, uint64_t seed, 
   hipLaunchKernelGGL(k_fill_perm, dim3(grid_for(nn)), dim3(kB), 0, s, order.as<int32_t>(), gptr.as<int32_t>(),
                      start.as<int32_t>(), nn, perm);
   ICPCG_HIP_TRY(hipGetLastError());
+  ICPCG_HIP_TRY(hipStreamSynchronize(s));
+  return ICPCG_OK;
+}
+
+// Block multicolour order: the caller partitions the rows into blocks
+// (blk[i] in [0, nblk), for instance mesh blocks of nodes); blocks coupled by
+// an entry of A are neighbours, block b takes the smallest colour not used by
+// its neighbours of lower id (sequential first fit in id order, computed by
+// JP rounds; on a block grid numbered like its nodes this is the 8-colour
+// parity pattern), and the rows are ordered by (colour of their block, block,
+// row).
+int block_color_order(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nnz, const int32_t *blk, int32_t nblk,
+                      int32_t *perm, int32_t *ncolours, hipStream_t s) {
+  int st;
+  DevBuf len, bad, qrp, key, val, kout, vout;
+  if (len.reserve((size_t)nblk * 8) || bad.reserve(4) || qrp.reserve(((size_t)nblk + 1) * 8))
+    return ICPCG_E_NOMEM;
+  ICPCG_HIP_TRY(hipMemsetAsync(len.p, 0, (size_t)nblk * 8, s));
+  ICPCG_HIP_TRY(hipMemsetAsync(bad.p, 0, 4, s));
+  hipLaunchKernelGGL(k_block_len, dim3(grid_for(n)), dim3(kB), 0, s, rp, n, blk, nblk,
+                     len.as<unsigned long long>(), bad.as<int>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  int hb = 0;
+  if ((st = read_int(bad.as<int>(), s, &hb))) return st;
+  if (hb) {
+    set_error("block_color_order: a block id is outside [0, nblk)");
+    return ICPCG_E_INVALID;
+  }
+  int64_t total = 0;
+  if ((st = scan_exclusive_i64(len.as<int64_t>(), qrp.as<int64_t>(), nblk, s, &total))) return st;
+  hipLaunchKernelGGL(k_set_at, dim3(1), dim3(1), 0, s, qrp.as<int64_t>(), (int64_t)nblk, total);
+  // each block's neighbour list: entries sorted (stably) by the block of their row
+  if (key.reserve(nnz * 4) || val.reserve(nnz * 4) || kout.reserve(nnz * 4) || vout.reserve(nnz * 4))
+    return ICPCG_E_NOMEM;
+  hipLaunchKernelGGL(k_entry_blocks, dim3(grid_for(n)), dim3(kB), 0, s, rp, ci, n, blk, key.as<uint32_t>(),
+                     val.as<uint32_t>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  if ((st = radix_sort_pairs(key.as<uint32_t>(), val.as<uint32_t>(), kout.as<uint32_t>(), vout.as<uint32_t>(), nnz,
+                             bits_for(nblk - 1), s)))
+    return st;
+  key.release();
+  val.release();
+  kout.release();
+  // colour the block graph: block v's list is "row" v of (qrp, vout)
+  DevBuf gptr, node_of, ca, cb;
+  if (gptr.reserve(((size_t)nblk + 1) * 4)) return ICPCG_E_NOMEM;
+  if ((st = fill_iota_u32(gptr.as<uint32_t>(), (int64_t)nblk + 1, s))) return st;
+  int32_t *colour = nullptr, maxc = 0;
+  if ((st = jp_colour(qrp.as<int64_t>(), vout.as<int32_t>(), gptr.as<int32_t>(), nblk, nblk, 0, true, node_of, ca, cb,
+                      &colour, &maxc, "block_color_order", s)))
+    return st;
+  *ncolours = maxc + 1;
+  // rows by (colour, block, row): stable sorts on the block, then the colour
+  DevBuf rows, rk, o1, k2, kk;
+  if (rows.reserve(n * 4) || rk.reserve(n * 4) || o1.reserve(n * 4) || k2.reserve(n * 4) || kk.reserve(n * 4))
+    return ICPCG_E_NOMEM;
+  if ((st = fill_iota_u32(rows.as<uint32_t>(), n, s))) return st;
+  if ((st = radix_sort_pairs(reinterpret_cast<const uint32_t *>(blk), rows.as<uint32_t>(), rk.as<uint32_t>(),
+                             o1.as<uint32_t>(), n, bits_for(nblk - 1), s)))
+    return st;
+  hipLaunchKernelGGL(k_row_colour_keys, dim3(grid_for(n)), dim3(kB), 0, s, o1.as<uint32_t>(), blk, colour, n,
+                     k2.as<uint32_t>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  if ((st = radix_sort_pairs(k2.as<uint32_t>(), o1.as<uint32_t>(), kk.as<uint32_t>(), reinterpret_cast<uint32_t *>(perm),
+                             n, bits_for(maxc), s)))
+    return st;
   ICPCG_HIP_TRY(hipStreamSynchronize(s));
   return ICPCG_OK;
 }

@@ -205,6 +205,18 @@ class Context:
         self._check(self.lib.icpcg_color_order(self.h, C.byref(a), C.c_uint64(seed), _ptr(perm), C.byref(nc)))
         return perm, nc.value
 
+    def block_color_order(self, A: CSR, block: torch.Tensor, nblocks: int = 0):
+        """Block multicolour order of a row partition (block: int32 tensor, block
+        id per row): (perm int32 tensor, new row -> old row; colour count)."""
+        self._bind()
+        b = block.to(device=A.val.device, dtype=torch.int32).contiguous()
+        nb = int(nblocks) if nblocks else (int(b.max().item()) + 1 if b.numel() else 1)
+        perm = torch.empty(A.n, dtype=torch.int32, device=A.val.device)
+        nc = C.c_int32()
+        a = A.cstruct()
+        self._check(self.lib.icpcg_block_color_order(self.h, C.byref(a), _ptr(b), nb, _ptr(perm), C.byref(nc)))
+        return perm, nc.value
+
     def permute(self, A: CSR, perm: torch.Tensor) -> CSR:
         """P A P^T."""
         self._bind()

@@ -15,6 +15,7 @@ from .elasticity import (  # noqa: F401
     traction_loads,
     rigid_body_modes,
     expected_sizes,
+    node_blocks,
 )
 from .small import (  # noqa: F401
     tridiagonal_spd,

@@ -281,6 +281,21 @@ def rigid_body_modes(E: int) -> np.ndarray:
     return M
 
 
+def node_blocks(E: int, bs: int) -> tuple[np.ndarray, int]:
+    """Partition of the rows of the E^3 clamped Q1 matrix into mesh blocks of
+    bs x bs x bs nodes (a node's 3 rows in one block): block id per row
+    (int32) and the block count. Input structure only (like coordinates)."""
+    N1 = E + 1
+    nb = -(-N1 // bs)
+    nbz = -(-E // bs)
+    node = np.arange(N1 * N1 * E)
+    I = node % N1
+    J = (node // N1) % N1
+    K = node // (N1 * N1)  # free layers 1..E, numbered from 0
+    b = (I // bs) + nb * ((J // bs) + nb * (K // bs))
+    return np.repeat(b, 3).astype(np.int32), int(nb * nb * nbz)
+
+
 def build_workload(name: str, with_rhs: bool = True):
     """Matrix and right-hand side(s) of a named synthetic workload.
     Returns (ElasticityProblem, B) with B of shape (n,) or (n, nrhs)."""

@@ -11,6 +11,7 @@ import oracle
 from oracle import order as OO
 import paper_2412_07127_amd as pkg
 from gpu_common import named_matrix, relerr, workload_problem
+from synth import node_blocks
 
 pytestmark = pytest.mark.gpu
 
@@ -90,16 +91,74 @@ def test_reordered_factor_and_solve_match_oracle(ctx):
     assert relerr(oracle.spmv(*A_h, x), b) <= 1e-8
 
 
+@pytest.mark.parametrize("key,E,bs", [("w:q1_8", 8, 2), ("w:q1_8", 8, 4), ("q1e4s2.0", 4, 2), ("w:q1_40", 40, 4)])
+def test_block_colour_order_bit_exact(ctx, key, E, bs):
+    A_h = named_matrix(key)
+    blk, nblk = node_blocks(E, bs)
+    perm, nc = ctx.block_color_order(to_gpu(A_h), torch.from_numpy(blk), nblk)
+    ref, col, nc_ref = OO.block_color_order(A_h, blk, nblk=nblk)
+    print(f"{key} blocks of {bs}^3 nodes: {nblk} blocks, {nc} colours")
+    assert nc == nc_ref
+    assert np.array_equal(perm.cpu().numpy(), ref)
+
+
+def test_block_colour_order_random_partition_and_bad_ids(ctx):
+    A_h = named_matrix("lap7")
+    n = len(A_h[0]) - 1
+    blk = np.random.default_rng(4).integers(0, 17, n).astype(np.int32)
+    nblk = 20  # blocks 17..19 are empty
+    perm, nc = ctx.block_color_order(to_gpu(A_h), torch.from_numpy(blk), nblk)
+    ref, _, nc_ref = OO.block_color_order(A_h, blk, nblk=nblk)
+    assert nc == nc_ref and np.array_equal(perm.cpu().numpy(), ref)
+    bad = blk.copy()
+    bad[7] = nblk
+    with pytest.raises(pkg.IcpcgError) as ei:
+        ctx.block_color_order(to_gpu(A_h), torch.from_numpy(bad), nblk)
+    assert ei.value.status == pkg._lib.E_INVALID
+
+
+def test_block_reordered_factor_and_solve_match_oracle(ctx):
+    prob, b = workload_problem("q1_8")
+    A_h = (prob.row_ptr, prob.col, prob.val)
+    blk, nblk = node_blocks(8, 2)
+    perm, nc = ctx.block_color_order(to_gpu(A_h), torch.from_numpy(blk), nblk)
+    Ap = ctx.permute(to_gpu(A_h), perm)
+    Lg, finfo = ctx.factor(Ap)
+    pn = perm.cpu().numpy()
+    Ap_h = OO.permute(A_h, pn)
+    st, L, alpha, _, _ = oracle.ic0_shifted(*Ap_h)
+    assert finfo["alpha"] == alpha
+    assert relerr(Lg.val.cpu().numpy(), L[2]) <= 1e-12
+    P = ctx.prec(Lg, "f64")
+    print(f"{nc} colours: supernode levels {P.info()['nsn_levels_L']}")
+    bp = ctx.permute_rows(perm, torch.from_numpy(b).cuda())
+    Xp, inf = ctx.solve(Ap, P, bp, rtol=1e-8)
+    U = oracle.transpose(*L)
+    ref = oracle.pcg(Ap_h, L, U, b[pn], rtol=1e-8)
+    k = inf[0]["iters"]
+    assert inf[0]["status"] == 0 and abs(k - ref["iters"]) <= 1
+    same_k = oracle.pcg(Ap_h, L, U, b[pn], rtol=0.0, max_iter=k, max_replace=0)
+    assert relerr(Xp.cpu().numpy(), same_k["x"]) <= 1e-10
+    x = ctx.permute_rows(perm, Xp, inverse=True).cpu().numpy()
+    assert relerr(oracle.spmv(*A_h, x), b) <= 1e-8
+
+
 def test_reordering_iterations_and_time(ctx):
-    """Natural vs multicolour order on the 40^3 workload: factor levels,
-    iterations and solve time (FP64, one right-hand side), as measured."""
+    """Natural vs multicolour vs block multicolour (4^3-node blocks) order on
+    the 40^3 workload: factor levels, iterations and solve time (FP64, one
+    right-hand side), as measured."""
     prob, b = workload_problem("q1_40")
     A = to_gpu((prob.row_ptr, prob.col, prob.val))
     bt = torch.from_numpy(b).cuda()
     rows = {}
-    for name in ("natural", "coloured"):
+    for name in ("natural", "coloured", "block4"):
         if name == "coloured":
             perm, nc = ctx.color_order(A, seed=0)
+            Am = ctx.permute(A, perm)
+            rhs = ctx.permute_rows(perm, bt)
+        elif name == "block4":
+            blk, nblk = node_blocks(40, 4)
+            perm, nc = ctx.block_color_order(A, torch.from_numpy(blk), nblk)
             Am = ctx.permute(A, perm)
             rhs = ctx.permute_rows(perm, bt)
         else:
@@ -122,5 +181,6 @@ def test_reordering_iterations_and_time(ctx):
         rows[name] = dict(colours=nc, levels=pi["nlevels_L"], sn_levels=pi["nsn_levels_L"],
                           iters=info[0]["iters"], p_time=round(tp, 4), cg_time=round(tc, 4),
                           ms_per_iter=round(1e3 * tc / info[0]["iters"], 3))
-    print("natural vs multicolour:", rows)
+    print("natural vs multicolour vs block multicolour:", rows)
     assert rows["coloured"]["sn_levels"] < rows["natural"]["sn_levels"]
+    assert rows["block4"]["sn_levels"] < rows["natural"]["sn_levels"]

@@ -98,3 +98,80 @@ def test_laplacian_single_row_nodes():
     perm, col, nc = O.color_order(A, seed=2)
     adj = O.node_graph(A, ptr)
     assert all(col[u] != col[v] for v, nb in enumerate(adj) for u in nb)
+
+
+# ------------------------------------------------- block multicolour order
+
+def test_block_colouring_of_a_block_grid_is_the_parity_pattern():
+    """Mesh blocks numbered like the nodes (x fastest): first fit in id order
+    on the 27-neighbour block grid gives the 8-colour parity pattern, colour
+    determined by (bx mod 2, by mod 2, bz mod 2)."""
+    from synth import node_blocks
+    E, bs = 7, 2
+    A = q1(E)
+    blk, nblk = node_blocks(E, bs)
+    perm, col, nc = O.block_color_order(A, blk, nblk=nblk)
+    nb = -(-(E + 1) // bs)
+    b = np.arange(nblk)
+    par = (b % nb) % 2 + 2 * (((b // nb) % nb) % 2) + 4 * ((b // (nb * nb)) % 2)
+    assert nc == 8
+    for p in range(8):  # one colour per parity class, and all different
+        assert len(set(col[par == p].tolist())) == 1
+    assert len({int(col[par == p][0]) for p in range(8)}) == 8
+
+
+def test_block_colouring_of_a_path_alternates():
+    """One block per row of a tridiagonal matrix: the block graph is a path, so
+    first fit in id order alternates two colours."""
+    A = dense_to_csr(np.diag(np.full(9, 4.0)) + np.diag(np.full(8, -1.0), 1) + np.diag(np.full(8, -1.0), -1))
+    perm, col, nc = O.block_color_order(A, np.arange(9))
+    assert nc == 2 and np.array_equal(col, np.arange(9) % 2)
+    assert np.array_equal(perm, np.r_[np.arange(0, 9, 2), np.arange(1, 9, 2)])
+
+
+@pytest.mark.parametrize("bs", [2, 3])
+def test_block_order_layout_and_colouring(bs):
+    from synth import node_blocks
+    E = 4
+    A = q1(E)
+    blk, nblk = node_blocks(E, bs)
+    perm, col, nc = O.block_color_order(A, blk, nblk=nblk)
+    n = len(A[0]) - 1
+    assert sorted(perm.tolist()) == list(range(n))
+    adj = O.block_graph(A, blk, nblk)
+    for b, nb in enumerate(adj):
+        assert all(col[c] != col[b] for c in nb)                # proper colouring of the blocks
+        assert all(b in adj[c] for c in nb)                     # symmetric pattern, symmetric graph
+    key = [(int(col[blk[r]]), int(blk[r]), int(r)) for r in perm]
+    assert key == sorted(key)                                   # rows by (colour, block, row)
+    # a node's three rows stay together and in order
+    pos = np.empty(n, np.int64)
+    pos[perm] = np.arange(n)
+    assert np.all(pos[1::3] == pos[0::3] + 1) and np.all(pos[2::3] == pos[0::3] + 2)
+
+
+def test_block_order_of_a_single_block_is_the_identity():
+    A = laplacian7(4, 3, 2)
+    n = len(A[0]) - 1
+    perm, col, nc = O.block_color_order(A, np.zeros(n, np.int64))
+    assert np.array_equal(perm, np.arange(n)) and nc == 1
+
+
+def test_block_ordered_factor_solves_the_same_system():
+    """IC(0)-PCG on the block-ordered system returns the permuted solution of the
+    original one (same iteration bound, same true residual)."""
+    from synth import node_blocks
+    E = 4
+    A = q1(E)
+    blk, nblk = node_blocks(E, 2)
+    perm, _, _ = O.block_color_order(A, blk, nblk=nblk)
+    Ap = O.permute(A, perm)
+    n = len(A[0]) - 1
+    b = np.random.default_rng(2).standard_normal(n)
+    st, L, alpha, _, _ = oracle.ic0_shifted(*Ap)
+    assert st == oracle.OK
+    out = oracle.pcg(Ap, L, oracle.transpose(*L), b[perm], rtol=1e-10)
+    x = np.empty(n)
+    x[perm] = out["x"]
+    r = b - oracle.spmv(*A, x)
+    assert np.linalg.norm(r) <= 1e-9 * np.linalg.norm(b)
