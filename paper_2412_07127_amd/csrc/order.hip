@@ -178,16 +178,27 @@ __global__ void k_entry_blocks(const int64_t *__restrict__ rp, const int32_t *__
   }
 }
 
-__global__ void k_block_len(const int64_t *__restrict__ rp, int64_t n, const int32_t *__restrict__ blk, int32_t nblk,
-                            unsigned long long *__restrict__ len, int *bad) {
-  for (int64_t i = gtid(); i < n; i += gstride()) {
-    const int32_t b = blk[i];
-    if (b < 0 || b >= nblk) {
-      atomicOr(bad, 1);
-      continue;
+__global__ void k_check_blocks(const int32_t *__restrict__ blk, int64_t n, int32_t nblk, int *bad) {
+  for (int64_t i = gtid(); i < n; i += gstride())
+    if (blk[i] < 0 || blk[i] >= nblk) atomicOr(bad, 1);
+}
+
+// After sorting the pairs by (row block, column block): keep the first of each
+// run of equal pairs, and drop a block's pairs with itself.
+__global__ void k_pair_keep(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b, int64_t m,
+                            int32_t *__restrict__ keep) {
+  for (int64_t t = gtid(); t < m; t += gstride())
+    keep[t] = (a[t] != b[t] && (t == 0 || a[t] != a[t - 1] || b[t] != b[t - 1])) ? 1 : 0;
+}
+
+__global__ void k_pair_compact(const uint32_t *__restrict__ a, const uint32_t *__restrict__ b,
+                               const int32_t *__restrict__ keep, const int32_t *__restrict__ pos, int64_t m,
+                               int32_t *__restrict__ nb, unsigned long long *__restrict__ cnt) {
+  for (int64_t t = gtid(); t < m; t += gstride())
+    if (keep[t]) {
+      nb[pos[t]] = (int32_t)b[t];
+      atomicAdd(&cnt[a[t]], 1ull);
     }
-    atomicAdd(&len[b], (unsigned long long)(rp[i + 1] - rp[i]));
-  }
 }
 
 __global__ void k_row_colour_keys(const uint32_t *__restrict__ rows, const int32_t *__restrict__ blk,
@@ -297,13 +308,10 @@ int color_order(const int64_t *rp, const int32_t *ci, int64_t n, uint64_t seed, 
 int block_color_order(const int64_t *rp, const int32_t *ci, int64_t n, int64_t nnz, const int32_t *blk, int32_t nblk,
                       int32_t *perm, int32_t *ncolours, hipStream_t s) {
   int st;
-  DevBuf len, bad, qrp, key, val, kout, vout;
-  if (len.reserve((size_t)nblk * 8) || bad.reserve(4) || qrp.reserve(((size_t)nblk + 1) * 8))
-    return ICPCG_E_NOMEM;
-  ICPCG_HIP_TRY(hipMemsetAsync(len.p, 0, (size_t)nblk * 8, s));
+  DevBuf bad;
+  if (bad.reserve(4)) return ICPCG_E_NOMEM;
   ICPCG_HIP_TRY(hipMemsetAsync(bad.p, 0, 4, s));
-  hipLaunchKernelGGL(k_block_len, dim3(grid_for(n)), dim3(kB), 0, s, rp, n, blk, nblk,
-                     len.as<unsigned long long>(), bad.as<int>());
+  hipLaunchKernelGGL(k_check_blocks, dim3(grid_for(n)), dim3(kB), 0, s, blk, n, nblk, bad.as<int>());
   ICPCG_HIP_TRY(hipGetLastError());
   int hb = 0;
   if ((st = read_int(bad.as<int>(), s, &hb))) return st;
@@ -311,21 +319,45 @@ int block_color_order(const int64_t *rp, const int32_t *ci, int64_t n, int64_t n
     set_error("block_color_order: a block id is outside [0, nblk)");
     return ICPCG_E_INVALID;
   }
-  int64_t total = 0;
-  if ((st = scan_exclusive_i64(len.as<int64_t>(), qrp.as<int64_t>(), nblk, s, &total))) return st;
-  hipLaunchKernelGGL(k_set_at, dim3(1), dim3(1), 0, s, qrp.as<int64_t>(), (int64_t)nblk, total);
-  // each block's neighbour list: entries sorted (stably) by the block of their row
-  if (key.reserve(nnz * 4) || val.reserve(nnz * 4) || kout.reserve(nnz * 4) || vout.reserve(nnz * 4))
+  // block pairs of the entries, sorted by (row block, column block): a stable
+  // sort on the column block, then on the row block
+  DevBuf key, val, k1, v1;
+  if (key.reserve(nnz * 4) || val.reserve(nnz * 4) || k1.reserve(nnz * 4) || v1.reserve(nnz * 4))
     return ICPCG_E_NOMEM;
   hipLaunchKernelGGL(k_entry_blocks, dim3(grid_for(n)), dim3(kB), 0, s, rp, ci, n, blk, key.as<uint32_t>(),
                      val.as<uint32_t>());
   ICPCG_HIP_TRY(hipGetLastError());
-  if ((st = radix_sort_pairs(key.as<uint32_t>(), val.as<uint32_t>(), kout.as<uint32_t>(), vout.as<uint32_t>(), nnz,
-                             bits_for(nblk - 1), s)))
+  const int bb = bits_for(nblk - 1);
+  if ((st = radix_sort_pairs(val.as<uint32_t>(), key.as<uint32_t>(), v1.as<uint32_t>(), k1.as<uint32_t>(), nnz, bb, s)))
     return st;
+  if ((st = radix_sort_pairs(k1.as<uint32_t>(), v1.as<uint32_t>(), key.as<uint32_t>(), val.as<uint32_t>(), nnz, bb, s)))
+    return st;
+  k1.release();
+  v1.release();
+  // distinct neighbours of each block (block v's list is "row" v of (qrp, nbr))
+  DevBuf keep, pos, nbr, cnt, qrp;
+  if (keep.reserve(nnz * 4) || pos.reserve(nnz * 4) || cnt.reserve((size_t)nblk * 8) ||
+      qrp.reserve(((size_t)nblk + 1) * 8))
+    return ICPCG_E_NOMEM;
+  hipLaunchKernelGGL(k_pair_keep, dim3(grid_for(nnz)), dim3(kB), 0, s, key.as<uint32_t>(), val.as<uint32_t>(), nnz,
+                     keep.as<int32_t>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  int32_t nedges = 0;
+  if ((st = scan_exclusive_i32(keep.as<int32_t>(), pos.as<int32_t>(), nnz, s, &nedges))) return st;
+  if (nbr.reserve((size_t)(nedges > 0 ? nedges : 1) * 4)) return ICPCG_E_NOMEM;
+  ICPCG_HIP_TRY(hipMemsetAsync(cnt.p, 0, (size_t)nblk * 8, s));
+  hipLaunchKernelGGL(k_pair_compact, dim3(grid_for(nnz)), dim3(kB), 0, s, key.as<uint32_t>(), val.as<uint32_t>(),
+                     keep.as<int32_t>(), pos.as<int32_t>(), nnz, nbr.as<int32_t>(), cnt.as<unsigned long long>());
+  ICPCG_HIP_TRY(hipGetLastError());
+  int64_t total = 0;
+  if ((st = scan_exclusive_i64(cnt.as<int64_t>(), qrp.as<int64_t>(), nblk, s, &total))) return st;
+  hipLaunchKernelGGL(k_set_at, dim3(1), dim3(1), 0, s, qrp.as<int64_t>(), (int64_t)nblk, total);
+  ICPCG_HIP_TRY(hipGetLastError());
   key.release();
   val.release();
-  kout.release();
+  keep.release();
+  pos.release();
+  DevBuf &vout = nbr;
   // colour the block graph: block v's list is "row" v of (qrp, vout)
   DevBuf gptr, node_of, ca, cb;
   if (gptr.reserve(((size_t)nblk + 1) * 4)) return ICPCG_E_NOMEM;
