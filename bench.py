@@ -309,8 +309,10 @@ def main():
             variants[name]["rel_diff_vs_fp64_gpu"] = torch.linalg.norm(xx - x64).item() / nx
         del Pb
 
+    tunes = {}
+
     def multi(order, Mx, Px, name, steps, warmup):
-        ctx.autotune(Mx, Px, args.nrhs)  # the width choice is setup, outside the timing
+        tunes[name] = ctx.autotune(Mx, Px, args.nrhs)  # the width choice is setup, outside the timing
         for _ in range(warmup):
             solve_in(order, Mx, Px, Bt, graph=True)
         torch.cuda.synchronize()
@@ -417,6 +419,9 @@ def main():
         "p_time_s": round(p_time, 4),
         "p_time_multicolour_s": round(p_time_c, 4),
         "ordering_s": round(order_time, 4),
+        "autotune": {k: dict(block_width=v["block_width"], ms_per_rhs_step=round(v["ms_per_rhs"], 4),
+                             ms_per_step_by_width={str(w): round(t, 4) for w, t in v["ms_per_step"].items()})
+                     for k, v in tunes.items()},
         "p_time_block_multicolour_s": round(p_time_b, 4),
         "ordering_block_multicolour_s": round(order_time_b, 4),
         "block_multicolour": dict(block_nodes=64, blocks=nblk, colours=ncol_b, alpha=finfo_b["alpha"],
