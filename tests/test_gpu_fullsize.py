@@ -9,6 +9,8 @@ adjoint); converged solves are checked through the true residual computed by
 the oracle's SpMV on the CPU.
 """
 
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -193,13 +195,25 @@ def test_q150_multi_rhs_inference_scale(ctx):
     prob = q1_elasticity(150, 1.5, 1004)
     Ah = (prob.row_ptr, prob.col, prob.val)
     A = pkg.CSR.from_numpy(*Ah)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     Lg, finfo = ctx.factor(A)
+    torch.cuda.synchronize()
+    t_fac = time.perf_counter() - t0
     P = ctx.prec(Lg, "f32")
     del Lg
     B = traction_loads(150, 16, 2004)
-    X, info = ctx.solve(A, P, torch.from_numpy(B).cuda(), rtol=1e-8)
+    Bt = torch.from_numpy(B).cuda()
+    M = ctx.matrix(A)
+    ctx.autotune(M, P, 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, info = ctx.solve(M, P, Bt, rtol=1e-8, use_graph=True)
+    torch.cuda.synchronize()
+    t_cg = time.perf_counter() - t0
     iters = [i["iters"] for i in info]
-    print(f"q150: alpha {finfo['alpha']} iters {min(iters)}..{max(iters)}")
+    print(f"q150: factor {t_fac:.2f} s alpha {finfo['alpha']}; 16 load cases {t_cg:.2f} s "
+          f"({t_cg / 16:.3f} s per RHS), iters {min(iters)}..{max(iters)}")
     assert all(i["status"] == 0 for i in info)
     Xh = X.cpu().numpy()
     for c in (0, 15):
