@@ -6,7 +6,11 @@
 // by its neighbours of higher (priority, id), with SplitMix64 priorities.
 // Jones-Plassmann rounds compute exactly that colouring: a node is decided
 // in the round after all of its higher-key neighbours are. The order sorts
-// nodes by (colour, id) and keeps each node's rows together.
+// nodes by (colour, id) and keeps each node's rows together. The block
+// variant colours a caller's partition of the rows (for instance mesh blocks)
+// in the same rounds, with block ids as priorities, and sorts the rows by
+// (colour, block, row). Also here: P A P^T and the row permutation of blocks
+// of vectors.
 #include <string>
 
 #include "internal.hpp"
@@ -357,13 +361,12 @@ int block_color_order(const int64_t *rp, const int32_t *ci, int64_t n, int64_t n
   val.release();
   keep.release();
   pos.release();
-  DevBuf &vout = nbr;
-  // colour the block graph: block v's list is "row" v of (qrp, vout)
+  // colour the block graph: block v's list is "row" v of (qrp, nbr)
   DevBuf gptr, node_of, ca, cb;
   if (gptr.reserve(((size_t)nblk + 1) * 4)) return ICPCG_E_NOMEM;
   if ((st = fill_iota_u32(gptr.as<uint32_t>(), (int64_t)nblk + 1, s))) return st;
   int32_t *colour = nullptr, maxc = 0;
-  if ((st = jp_colour(qrp.as<int64_t>(), vout.as<int32_t>(), gptr.as<int32_t>(), nblk, nblk, 0, true, node_of, ca, cb,
+  if ((st = jp_colour(qrp.as<int64_t>(), nbr.as<int32_t>(), gptr.as<int32_t>(), nblk, nblk, 0, true, node_of, ca, cb,
                       &colour, &maxc, "block_color_order", s)))
     return st;
   *ncolours = maxc + 1;
