@@ -124,6 +124,8 @@ template <int SLOTS> struct GrpDepth {
   static constexpr int v = (88 + SLOTS - 1) / SLOTS > 11 ? 11 : (88 + SLOTS - 1) / SLOTS;
 };
 
+// At least three waves per SIMD (at most 168 VGPRs): the 16-column variant
+// with the fused dot would otherwise settle a few registers above it.
 template <int R, int SLOTS, bool DOT, int CPL, int QD = GrpDepth<SLOTS>::v>
 __global__ __launch_bounds__(kBlock, 3) void k_spmv_grp(const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                      int64_t ngroups, const SpGroup *__restrict__ grec,
