@@ -201,10 +201,21 @@ def test_q150_multi_rhs_inference_scale(ctx):
     torch.cuda.synchronize()
     t_fac = time.perf_counter() - t0
     P = ctx.prec(Lg, "f32")
+    P64 = ctx.prec(Lg, "f64")
     del Lg
     B = traction_loads(150, 16, 2004)
     Bt = torch.from_numpy(B).cuda()
     M = ctx.matrix(A)
+    # the comparison of the batched solve: sequential FP64 solves (one timed, x16)
+    b0 = Bt[:, 0].contiguous()
+    ctx.solve(M, P64, b0, rtol=1e-8, max_iter=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x0, info0 = ctx.solve(M, P64, b0, rtol=1e-8)
+    torch.cuda.synchronize()
+    t_64 = time.perf_counter() - t0
+    assert info0[0]["status"] == 0 and info0[0]["true_relres"] <= 1e-8
+    del P64
     ctx.autotune(M, P, 16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -213,7 +224,9 @@ def test_q150_multi_rhs_inference_scale(ctx):
     t_cg = time.perf_counter() - t0
     iters = [i["iters"] for i in info]
     print(f"q150: factor {t_fac:.2f} s alpha {finfo['alpha']}; 16 load cases {t_cg:.2f} s "
-          f"({t_cg / 16:.3f} s per RHS), iters {min(iters)}..{max(iters)}")
+          f"({t_cg / 16:.3f} s per RHS), iters {min(iters)}..{max(iters)}; one FP64 solve "
+          f"{t_64:.2f} s ({info0[0]['iters']} it), 16 sequential = {16 * t_64:.1f} s, "
+          f"ratio {16 * t_64 / t_cg:.1f}x")
     assert all(i["status"] == 0 for i in info)
     Xh = X.cpu().numpy()
     for c in (0, 15):
