@@ -11,8 +11,9 @@ FP32 and FP64 recurrences. The value is solved right-hand sides per second
 over the timed steps (inputs resident in HBM). Reported beside it:
 single-RHS solves in FP64, FP32-L and BF16-L, and the multicolour node order
 (the right-hand sides permuted in and the solutions back inside the timing)
-for one FP64 solve and one 16-RHS step, with the factors (P-time) and the
-ordering time separately.
+and the block multicolour order (4^3-node mesh blocks) for one FP64 solve and
+one 16-RHS step each, with the factors (P-time) and the ordering time
+separately.
 
 One JSON line on stdout; progress on stderr.
 """
@@ -252,6 +253,7 @@ def main():
     Mb = ctx.matrix(Ab)
     Lb, finfo_b, p_time_b = timed_factor(Ab)
     Pb64 = ctx.prec(Lb, "f64")
+    Pb32 = ctx.prec(Lb, "f32")
     pinfo_b = Pb64.info()
     log(f"block multicolour: {ncol_b} colours over {nblk} blocks, ordering {order_time_b:.3f} s, factor "
         f"{p_time_b:.3f} s, alpha={finfo_b['alpha']}, supernode levels {pinfo_b['nsn_levels_L']}")
@@ -335,6 +337,7 @@ def main():
     # multicolour order, 16 load cases (reported beside the headline)
     if not args.skip_single:
         multi("colour", Mc, Pc32, "multi16_fp32_L_multicolour", 1, 0)
+        multi("block", Mb, Pb32, "multi16_fp32_L_block_multicolour", 1, 1)
     # headline: natural order, 16 load cases, FP32 factor, FP64 recurrences
     total, step_s = multi("natural", M, P32, "multi16_fp32_L", args.steps, args.warmup)
     value = args.nrhs * args.steps / total
@@ -342,6 +345,7 @@ def main():
     # per-kernel live timing at the headline's launch shape
     R = args.nrhs if args.nrhs in (1, 2, 4, 8, 16) else 16
     kt = time_kernels(ctx, M, P32, R, args.kernel_reps, torch)
+    kt_b = time_kernels(ctx, Mb, Pb32, R, args.kernel_reps, torch) if not args.skip_single else None
     n, nnzA, nnzL = prob.n, prob.nnz, pinfo["nnz"]
     ngroups, gcols = grouped_pattern(prob.row_ptr, prob.col)
     nsnL, nsnU = pinfo["nsupernodes_L"], pinfo["nsupernodes_U"]
@@ -354,6 +358,14 @@ def main():
     }
     for k_, v in kernels.items():
         log(f"kernel {k_}: {v['s'] * 1e3:.3f} ms, {v['gbs']:.0f} GB/s algorithmic")
+    kernels_b = None
+    if kt_b is not None:
+        _, trsvLb = kernel_bytes(n, nnzA, nnzL, pinfo_b["nsupernodes_L"], R, 4, 8, 4, ngroups, gcols)
+        _, trsvUb = kernel_bytes(n, nnzA, nnzL, pinfo_b["nsupernodes_U"], R, 4, 4, 4, ngroups, gcols)
+        # the SpMV of the permuted matrix is costed at the natural pattern's grouping
+        kernels_b = {k_: dict(ms=round(kt_b[k_] * 1e3, 4), algorithmic_GBs=round(b_ / kt_b[k_] / 1e9, 1))
+                     for k_, b_ in (("spmv", spmv_b), ("trsv_L", trsvLb), ("trsv_U", trsvUb))}
+        log(f"block multicolour kernels: {kernels_b}")
     dom = max(kernels, key=lambda k_: kernels[k_]["s"])
     roof = dict(bound="hbm", kernel=dom, achieved=round(kernels[dom]["gbs"], 1), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(kernels[dom]["gbs"] / PEAK_HBM_GBS, 4), traffic=recorded_traffic(dom),
@@ -425,7 +437,7 @@ def main():
         "p_time_block_multicolour_s": round(p_time_b, 4),
         "ordering_block_multicolour_s": round(order_time_b, 4),
         "block_multicolour": dict(block_nodes=64, blocks=nblk, colours=ncol_b, alpha=finfo_b["alpha"],
-                                  supernode_levels=pinfo_b["nsn_levels_L"]),
+                                  supernode_levels=pinfo_b["nsn_levels_L"], kernels=kernels_b),
         "prec_setup_s": round(prec_time, 4),
         "factor": dict(alpha=finfo["alpha"], restarts=finfo["restarts"], row_levels=finfo["nlevels"],
                        supernode_levels_L=pinfo["nsn_levels_L"], supernode_levels_U=pinfo["nsn_levels_U"]),
