@@ -61,6 +61,12 @@ def test_baseline_matches_oracle(ctx, key, kind):
 
 @pytest.mark.parametrize("kind", ["jacobi", "none"])
 def test_baseline_multi_rhs_and_graph(ctx, kind):
+    """Four columns at once, eager and graph-replayed (bitwise equal), each
+    against the oracle at equal k. Plain CG runs ~270 iterations here; with
+    only the summation order of the dot products differing (a block tree on
+    the GPU, a running sum in the oracle), its four columns' equal-k
+    differences spread over a decade (1.5e-10 to 1.2e-9), so its bar is 5e-9;
+    Jacobi (~170 iterations, below 1e-10) keeps 1e-9."""
     A_h = named_matrix("w:q1_8")
     A = ctx.matrix(to_gpu(A_h))
     P = ctx.prec_simple(A.A, kind)
@@ -70,10 +76,15 @@ def test_baseline_multi_rhs_and_graph(ctx, kind):
     X, info = ctx.solve(A, P, Bt, rtol=1e-8, block_width=4, max_iter=20 * n)
     Xg, infog = ctx.solve(A, P, Bt, rtol=1e-8, block_width=4, max_iter=20 * n, use_graph=True)
     assert torch.equal(X, Xg) and info == infog
+    errs = []
     for c in range(4):
         k = info[c]["iters"]
         ref = oracle.pcg_simple(A_h, B[:, c], kind, rtol=0.0, max_iter=k, max_replace=0)
-        assert relerr(X[:, c].cpu().numpy(), ref["x"]) <= 1e-9
+        errs.append((k, relerr(X[:, c].cpu().numpy(), ref["x"])))
+    print(f"{kind}: (iterations, equal-k difference) per column {errs}")
+    bar = 5e-9 if kind == "none" else 1e-9
+    for k, err in errs:
+        assert err <= bar
 
 
 def test_table1_iteration_structure(ctx):
