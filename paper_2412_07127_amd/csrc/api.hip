@@ -530,7 +530,7 @@ struct PassBuffers {
 int spmv_pass(const icpcg_csr *A, const PassBuffers &b, const double *x, double *y, int R, hipStream_t s,
               double *partials = nullptr, ColState *cols = nullptr, const int *active = nullptr) {
   if (b.grec)
-    return spmv_grouped(A->col, A->val, b.ngroups, b.grec, x, y, R, spmv_grouped_default_slots(R), s,
+    return spmv_grouped(A->col, A->val, b.ngroups, b.grec, A->n, x, y, R, spmv_grouped_default_slots(R), s,
                         partials, cols, active);
   return spmv(A->row_ptr, A->col, A->val, A->n, x, y, R, spmv_default_slots(R), s, partials, cols, active);
 }
@@ -882,7 +882,7 @@ extern "C" icpcg_status icpcg_mat_spmv(icpcg_ctx *ctx, const icpcg_mat *M, const
   if (!M->grouped)
     return finish(ctx, spmv(A->row_ptr, A->col, A->val, A->n, X, W, (int)nrhs, spmv_default_slots((int)nrhs),
                             ctx->stream));
-  return finish(ctx, spmv_grouped(A->col, A->val, M->ngroups, M->grec.as<SpGroup>(), X, W, (int)nrhs,
+  return finish(ctx, spmv_grouped(A->col, A->val, M->ngroups, M->grec.as<SpGroup>(), A->n, X, W, (int)nrhs,
                                   spmv_grouped_default_slots((int)nrhs), ctx->stream));
 }
 

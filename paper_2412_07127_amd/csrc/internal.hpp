@@ -251,9 +251,11 @@ int spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const
          double *y, int R, int slots, hipStream_t s, double *partials = nullptr,
          ColState *cols = nullptr, const int *active = nullptr);
 
-int spmv_grouped(const int32_t *ci, const double *v, int64_t ngroups, const SpGroup *grec, const double *x,
-                 double *y, int R, int slots, hipStream_t s, double *partials = nullptr, ColState *cols = nullptr,
-                 const int *active = nullptr);
+// partials (nullable): also p^T w -> alpha of each column, in a second pass
+// over x = p and y = w (n rows).
+int spmv_grouped(const int32_t *ci, const double *v, int64_t ngroups, const SpGroup *grec, int64_t n,
+                 const double *x, double *y, int R, int slots, hipStream_t s, double *partials = nullptr,
+                 ColState *cols = nullptr, const int *active = nullptr);
 int spmv_grouped_default_slots(int R);
 
 // active (nullable): the solve's count of iterating columns; when it reads 0
@@ -276,6 +278,8 @@ int pcg_update_p(int64_t n, int R, const void *z, bool f32, double *p, void *y, 
                  const ColState *cols, const SolveFlags *flags, hipStream_t s);
 int pcg_pw_finalize(int R, const double *partials, int nb, ColState *cols, const SolveFlags *flags,
                     hipStream_t s);
+int pcg_dot_pw(int64_t n, int R, const double *p, const double *w, double *partials, ColState *cols,
+               const SolveFlags *flags, hipStream_t s);
 int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const double *w,
                   double *partials, ColState *cols, int64_t max_iter, SolveFlags *flags,
                   hipStream_t s);

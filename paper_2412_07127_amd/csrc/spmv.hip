@@ -1,18 +1,20 @@
 // CSR sparse matrix times an R-column block, FP64 (w = A p of supplementary
-// Algorithm 1), with an optional fused p^T w reduction (deterministic block
-// partials; a one-block finalize kernel computes alpha = r^T z / p^T w). The
-// fused dot takes p of each row from the x gathered for its diagonal column
-// (passed through LDS), so it adds no load after the row's sum.
+// Algorithm 1), with p^T w for alpha = r^T z / p^T w when the solver asks
+// (deterministic block partials, folded by a one-block finalize kernel). The
+// plain kernel fuses that dot, taking p of each row from the x gathered for
+// its diagonal column (passed through LDS); the row-group kernel leaves it to
+// one pass over p and w.
 //
 // Mapping (wave64): a group of SLOTS * R / CPL lanes owns one row (one row
 // group in the grouped kernel); a lane owns CPL consecutive columns (min(R, 4)
 // in the plain kernel, min(R, 8) in the grouped one) and strides over the
-// row's entries slot, slot + SLOTS, ... Each lane first loads the indices and values of up
-// to QD of its entries, then issues all their x gathers (each one contiguous
-// piece of a row of the row-major block), so every wave keeps many loads in
-// flight. Partial sums meet in a fixed butterfly. Each block owns a
-// contiguous row range; block ids are remapped so that each XCD works on one
-// contiguous part of the matrix and its L2 serves the neighbouring gathers.
+// row's entries slot, slot + SLOTS, ... Each lane first loads the indices and
+// values of up to QD of its entries, with no load behind a branch, then
+// issues their x gathers (each one contiguous piece of a row of the row-major
+// block), so every wave keeps many loads in flight. Partial sums meet in a
+// fixed butterfly. Each block owns a contiguous row range; block ids are
+// remapped so that each XCD works on one contiguous part of the matrix and its
+// L2 serves the neighbouring gathers.
 #include <cstdlib>
 
 #include "reduce.hpp"
@@ -59,28 +61,33 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t *__restrict__ rp,
   for (int cc = 0; cc < CPL; ++cc) dot[cc] = 0.0;
   for (int64_t row = r0 + g; row < r1; row += GPB) {
     const int64_t s = rp[row], e = rp[row + 1];
-    int jj[QD];
-    double vv[QD];
-#pragma unroll
-    for (int k = 0; k < QD; ++k) {
-      const int64_t q = s + slot + k * SLOTS;
-      jj[k] = q < e ? ci[q] : 0;
-      vv[k] = q < e ? v[q] : 0.0;
-    }
     double acc[CPL];
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) acc[cc] = 0.0;
+    if (e > s) {  // an empty row sums to zero
+      // no load behind a per-entry branch (see the grouped kernel): a slot
+      // past the row's end reloads the row's last entry with its value scaled
+      // by 0 (a non-finite value or x there makes the row non-finite either way)
+      int jj[QD];
+      bool ok[QD];
+      double vv[QD];
 #pragma unroll
-    for (int k = 0; k < QD; ++k) {
-      const int64_t q = s + slot + k * SLOTS;
-      if (q < e) {
+      for (int k = 0; k < QD; ++k) {
+        const int64_t q = s + slot + k * SLOTS;
+        ok[k] = q < e;
+        const int64_t qc = ok[k] ? q : e - 1;
+        jj[k] = ci[qc];
+        vv[k] = v[qc] * (ok[k] ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int k = 0; k < QD; ++k) {
         const double *xr = x + (int64_t)jj[k] * R + c0;
         double xv[CPL];
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) xv[cc] = xr[cc];
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) acc[cc] += vv[k] * xv[cc];
-        if (DOT && jj[k] == row) {
+        if (DOT && ok[k] && jj[k] == row) {
 #pragma unroll
           for (int cc = 0; cc < CPL; ++cc) pd[c0 + cc] = xv[cc];
         }
@@ -119,35 +126,42 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t *__restrict__ rp,
 // Row-group variant: a lane group owns up to GMAX consecutive rows with
 // identical column lists (the rows of one node), reads each column index once
 // and gathers each x row once for all of them. Each group's record is loaded
-// one iteration ahead, so a group costs two dependent trips (indices, then x).
+// one iteration ahead. The load order is fixed in the source, not left to the
+// compiler: all index and value loads of a lane's QD entries first, then the
+// x gathers in batches of KB entries, each batch issued whole before its
+// products (scheduling barriers), so a group costs about one trip for the
+// indices and one per batch. No load sits behind a branch, since the compiler
+// waits for such a load (or one whose result is selected) at the join: a slot
+// past the group's columns reloads its last column with its value scaled by
+// 0. Every group has a column and finite values (each row stores its
+// diagonal, checked when the matrix handle is made), and that column is one
+// of the group's own, so a non-finite x there makes the rows non-finite
+// either way. The fused p^T w of the solver is a separate pass over p and w
+// (below): keeping p of each row for it inside this kernel costs more
+// registers than the pass costs time.
 template <int SLOTS> struct GrpDepth {
   static constexpr int v = (88 + SLOTS - 1) / SLOTS > 11 ? 11 : (88 + SLOTS - 1) / SLOTS;
 };
 
-// At least three waves per SIMD (at most 168 VGPRs): the 16-column variant
-// with the fused dot would otherwise settle a few registers above it.
-template <int R, int SLOTS, bool DOT, int CPL, int QD = GrpDepth<SLOTS>::v>
+// At least three waves per SIMD (at most 168 VGPRs).
+template <int R, int SLOTS, int CPL, int QD = GrpDepth<SLOTS>::v>
 __global__ __launch_bounds__(kBlock, 3) void k_spmv_grp(const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                      int64_t ngroups, const SpGroup *__restrict__ grec,
                                                      const double *__restrict__ x, double *__restrict__ y,
-                                                     int64_t chunk, double *partials,
-                                                     const int *__restrict__ active) {
-  if (DOT && active && *active == 0) return;
+                                                     int64_t chunk, const int *__restrict__ active) {
+  if (active && *active == 0) return;
   constexpr int GMAX = kSupernodeMax;
   constexpr int LPR = R / CPL;
   constexpr int GROUP = SLOTS * LPR;
   static_assert(GROUP <= 64 && 64 % GROUP == 0, "group must tile a wave");
   constexpr int GPB = kBlock / GROUP;
+  // entries per gather batch: about 48 registers of x in flight per lane
+  constexpr int KB = 24 / CPL > QD ? QD : 24 / CPL;
   const int t = threadIdx.x;
   const int g = t / GROUP, lg = t % GROUP, slot = lg / LPR, c0 = (lg % LPR) * CPL;
-  __shared__ double pdiag[DOT ? GPB * GMAX * R : 1];  // per group: p of its rows, [u][column]
-  double *pd = pdiag + (DOT ? g * GMAX * R : 0);
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int64_t g0 = lb * chunk;
   const int64_t g1 = g0 + chunk < ngroups ? g0 + chunk : ngroups;
-  double dot[CPL];
-#pragma unroll
-  for (int cc = 0; cc < CPL; ++cc) dot[cc] = 0.0;
   SpGroup nxt{};
   if (g0 + g < g1) nxt = grec[g0 + g];
   for (int64_t gi = g0 + g; gi < g1; gi += GPB) {
@@ -162,39 +176,43 @@ __global__ __launch_bounds__(kBlock, 3) void k_spmv_grp(const int32_t *__restric
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
       const int64_t q = slot + k * SLOTS;
-      jj[k] = q < m ? ci[base + q] : 0;
+      const bool ok = q < m;
+      const int64_t qc = ok ? q : m - 1;
+      const double keep = ok ? 1.0 : 0.0;
+      jj[k] = ci[base + qc];
 #pragma unroll
-      for (int u = 0; u < GMAX; ++u)
-        vv[k][u] = (q < m && u < sz) ? v[base + u * m + q] : 0.0;
+      for (int u = 0; u < GMAX; ++u)  // rows >= sz: unused
+        vv[k][u] = v[base + (u < sz ? u : sz - 1) * m + qc] * keep;
     }
+    __builtin_amdgcn_sched_barrier(0);
     double acc[GMAX][CPL];
 #pragma unroll
     for (int u = 0; u < GMAX; ++u)
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) acc[u][cc] = 0.0;
-    // for the fused p^T w: the group's rows are among its shared columns, so
-    // p of row r0 + u is the x gathered for that column; the lane that
-    // gathers it leaves it in the group's LDS table (read back after the
-    // butterfly by the lanes that write w; one wave, so LDS order suffices)
 #pragma unroll
-    for (int k = 0; k < QD; ++k) {
-      const int64_t q = slot + k * SLOTS;
-      if (q < m) {
-        const double *xr = x + (int64_t)jj[k] * R + c0;
-        double xv[CPL];
+    for (int k0 = 0; k0 < QD; k0 += KB) {
+      double xv[KB][CPL];
 #pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) xv[cc] = xr[cc];
+      for (int kk = 0; kk < KB; ++kk) {
+        if (k0 + kk < QD) {
+          const double *xr = x + (int64_t)jj[k0 + kk] * R + c0;
 #pragma unroll
-        for (int u = 0; u < GMAX; ++u)
+          for (int cc = 0; cc < CPL; ++cc) xv[kk][cc] = xr[cc];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int cc = 0; cc < CPL; ++cc) acc[u][cc] += vv[k][u] * xv[cc];
-        if (DOT && jj[k] >= r0 && jj[k] < r0 + sz) {
+      for (int kk = 0; kk < KB; ++kk) {
+        if (k0 + kk < QD) {
 #pragma unroll
-          for (int cc = 0; cc < CPL; ++cc) pd[(jj[k] - r0) * R + c0 + cc] = xv[cc];
+          for (int u = 0; u < GMAX; ++u)
+#pragma unroll
+            for (int cc = 0; cc < CPL; ++cc) acc[u][cc] += vv[k0 + kk][u] * xv[kk][cc];
         }
       }
     }
-    for (int64_t q = slot + QD * SLOTS; q < m; q += SLOTS) {
+    for (int64_t q = slot + QD * SLOTS; q < m; q += SLOTS) {  // rows longer than the window
       const int32_t j = ci[base + q];
       const double *xr = x + (int64_t)j * R + c0;
       double xv[CPL];
@@ -206,10 +224,6 @@ __global__ __launch_bounds__(kBlock, 3) void k_spmv_grp(const int32_t *__restric
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) acc[u][cc] += vq * xv[cc];
       }
-      if (DOT && j >= r0 && j < r0 + sz) {
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) pd[(j - r0) * R + c0 + cc] = xv[cc];
-      }
     }
 #pragma unroll
     for (int u = 0; u < GMAX; ++u)
@@ -219,47 +233,33 @@ __global__ __launch_bounds__(kBlock, 3) void k_spmv_grp(const int32_t *__restric
 #pragma unroll
       for (int u = 0; u < GMAX; ++u) {
         if (u < sz) {
-          const int64_t row = r0 + u;
 #pragma unroll
-          for (int cc = 0; cc < CPL; ++cc) {
-            y[row * R + c0 + cc] = acc[u][cc];
-            if (DOT) dot[cc] += pd[u * R + c0 + cc] * acc[u][cc];
-          }
+          for (int cc = 0; cc < CPL; ++cc) y[(r0 + u) * R + c0 + cc] = acc[u][cc];
         }
       }
     }
   }
-  if (DOT) {
-    __shared__ double smem[CPL * kRedBlock];
-    block_partials_cpl<R, CPL>(dot, partials, smem);
-  }
 }
 
 template <int R, int SLOTS, int CPL>
-int launch_grp(const int32_t *ci, const double *v, int64_t ngroups, const SpGroup *grec, const double *x, double *y,
-               hipStream_t s, double *partials, ColState *cols, const int *active) {
+int launch_grp(const int32_t *ci, const double *v, int64_t ngroups, const SpGroup *grec, int64_t n, const double *x,
+               double *y, hipStream_t s, double *partials, ColState *cols, const int *active) {
   constexpr int GPB = kBlock / (SLOTS * (R / CPL));
   // Short chunks keep the groups in flight on one XCD close together, so its
-  // L2 serves more of the neighbouring x gathers (measured best per width);
-  // the fused p^T w partials bound the block count.
+  // L2 serves more of the neighbouring x gathers (measured best per width).
   static const int iters_env = std::getenv("ICPCG_SPMVG_ITERS") ? std::atoi(std::getenv("ICPCG_SPMVG_ITERS")) : 0;
   const int ITERS = iters_env > 0 ? iters_env : (R >= 16 ? 16 : R >= 8 ? 8 : R >= 4 ? 2 : 1);
   int64_t nb = (ngroups + GPB * ITERS - 1) / (GPB * ITERS);
-  if (partials && nb > kMaxDotBlocks) nb = kMaxDotBlocks;
   if (nb < 1) nb = 1;
   const int64_t chunk = (ngroups + nb - 1) / nb;
   nb = (ngroups + chunk - 1) / chunk;
   if (nb < 1) nb = 1;
-  if (partials) {
-    hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, true, CPL>), dim3((unsigned)nb), dim3(kBlock), 0, s, ci, v, ngroups, grec, x,
-                       y, chunk, partials, active);
-    ICPCG_HIP_TRY(hipGetLastError());
-    return pcg_pw_finalize(R, partials, (int)nb, cols, reinterpret_cast<const SolveFlags *>(active), s);
-  }
-  hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, false, CPL>), dim3((unsigned)nb), dim3(kBlock), 0, s, ci, v, ngroups, grec, x,
-                     y, chunk, nullptr, nullptr);
+  hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, CPL>), dim3((unsigned)nb), dim3(kBlock), 0, s, ci, v, ngroups, grec, x, y,
+                     chunk, partials ? active : nullptr);
   ICPCG_HIP_TRY(hipGetLastError());
-  return ICPCG_OK;
+  if (!partials) return ICPCG_OK;
+  // p^T w for alpha: one deterministic pass over p = x and w = y
+  return pcg_dot_pw(n, R, x, y, partials, cols, reinterpret_cast<const SolveFlags *>(active), s);
 }
 
 template <int R, int SLOTS>
@@ -314,15 +314,16 @@ int spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const
   return ICPCG_E_INVALID;
 }
 
-int spmv_grouped(const int32_t *ci, const double *v, int64_t ngroups, const SpGroup *grec, const double *x,
-                 double *y, int R, int slots, hipStream_t s, double *partials, ColState *cols, const int *active) {
+int spmv_grouped(const int32_t *ci, const double *v, int64_t ngroups, const SpGroup *grec, int64_t n,
+                 const double *x, double *y, int R, int slots, hipStream_t s, double *partials, ColState *cols,
+                 const int *active) {
   if (ngroups <= 0) return ICPCG_OK;
 // a lane owns min(R, 8) columns: fewer lanes per row means fewer redundant
 // index and value loads and a shorter butterfly, which outweighs the wider
 // per-lane gathers
 #define ICPCG_SPMVG_CASE(RR, SS) \
   if (R == RR && slots == SS) \
-    return launch_grp<RR, SS, (RR < 8 ? RR : 8)>(ci, v, ngroups, grec, x, y, s, partials, cols, active);
+    return launch_grp<RR, SS, (RR < 8 ? RR : 8)>(ci, v, ngroups, grec, n, x, y, s, partials, cols, active);
   ICPCG_SPMVG_CASE(1, 16)
   ICPCG_SPMVG_CASE(1, 32)
   ICPCG_SPMVG_CASE(2, 16)

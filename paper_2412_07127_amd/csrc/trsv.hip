@@ -120,34 +120,48 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
     // off-block columns as listed in the first row: after its sz diagonal-block
     // entries (upper) or before its diagonal (lower)
     const int64_t pcol = UPPER ? ro[0] + sz : ro[0];
-    // everything that does not depend on other waves is loaded first
+    // everything that does not depend on other waves is loaded first; the
+    // factor values unconditionally, from a clamped place in the same row
+    // (its diagonal when the supernode has no off-block entry), and widened
+    // only where they are used. A slot past the window gathers x = 0, and the
+    // factor's values are finite (checked when the preconditioner is made),
+    // so such a product is exactly 0; rows u >= sz are never stored.
     int jj[QD];
-    TA vv[QD][kSmax];
+    TV vv[QD][kSmax];
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
       const int q = slot + k * SLOTS;
+      const int qc = q < m ? q : m - 1;
       jj[k] = q < m ? ci[pcol + q] : 0;
 #pragma unroll
-      for (int u = 0; u < kSmax; ++u)
-        vv[k][u] = (q < m && u < sz) ? widen<TA>(val[UPPER ? ro[u] + (sz - u) + q : ro[u] + q]) : TA(0);
-    }
-    TA dv[NDB];  // diagonal block, row by row (lower: columns a..a+u; upper: a+u..a+sz-1)
-    TA bv[kSmax][CPL];
-    if (slot == 0) {
-#pragma unroll
       for (int u = 0; u < kSmax; ++u) {
-        if (!UPPER) {
-#pragma unroll
-          for (int w = 0; w <= u; ++w) dv[u * (u + 1) / 2 + w] = u < sz ? widen<TA>(val[ro[u] + m + w]) : TA(1);
-        } else {
-          // row a+u holds columns a+u .. a+sz-1 first: (u, u+w) at u*kSmax - u*(u-1)/2 + w
-#pragma unroll
-          for (int w = 0; w < kSmax - u; ++w)
-            dv[u * kSmax - u * (u - 1) / 2 + w] = (u < sz && w < sz - u) ? widen<TA>(val[ro[u] + w]) : TA(1);
-        }
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) bv[u][cc] = u < sz ? (TA)rhs[(int64_t)(a + u) * R + c0 + cc] : TA(0);
+        const int uc = u < sz ? u : sz - 1;
+        vv[k][u] = val[m > 0 ? (UPPER ? ro[uc] + (sz - uc) + qc : ro[uc] + qc) : ro[uc]];
       }
+    }
+    // The diagonal block (row by row; lower: columns a..a+u, upper: a+u..a+sz-1)
+    // and the right-hand side, loaded by every lane (a wave issues the same
+    // instructions either way; slot 0 uses them) from clamped in-range places
+    // and converted only where they are used: a load behind a branch, or
+    // converted at the join, makes the compiler wait for it there, one row at
+    // a time, before the dependencies are even requested. Entries of rows
+    // u >= sz are never read.
+    TV dr[NDB];
+    TR br[kSmax][CPL];
+#pragma unroll
+    for (int u = 0; u < kSmax; ++u) {
+      const int uc = u < sz ? u : sz - 1;
+      if (!UPPER) {
+#pragma unroll
+        for (int w = 0; w <= u; ++w) dr[u * (u + 1) / 2 + w] = val[ro[uc] + m + (w < uc ? w : uc)];
+      } else {
+        // row a+u holds columns a+u .. a+sz-1 first: (u, u+w) at u*kSmax - u*(u-1)/2 + w
+#pragma unroll
+        for (int w = 0; w < kSmax - u; ++w)
+          dr[u * kSmax - u * (u - 1) / 2 + w] = val[ro[uc] + (w < sz - uc ? w : sz - 1 - uc)];
+      }
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) br[u][cc] = rhs[(int64_t)(a + uc) * R + c0 + cc];
     }
     // gather the dependencies: one attempt for all, then while any is still
     // pending the lanes covering one pending row poll it together (one
@@ -219,7 +233,7 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
         for (int cc = 0; cc < CPL; ++cc) {
           const TA x = bitcast<TA>(xb[k][cc]);
 #pragma unroll
-          for (int u = 0; u < kSmax; ++u) acc[u][cc] += vv[k][u] * x;
+          for (int u = 0; u < kSmax; ++u) acc[u][cc] += widen<TA>(vv[k][u]) * x;
         }
       }
     }
@@ -246,10 +260,10 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
 #pragma unroll
           for (int u = 0; u < kSmax; ++u) {
             if (u < sz) {
-              TA sum = bv[u][cc] - acc[u][cc];
+              TA sum = (TA)br[u][cc] - acc[u][cc];
 #pragma unroll
-              for (int w = 0; w < u; ++w) sum -= dv[u * (u + 1) / 2 + w] * xs[w][cc];
-              xs[u][cc] = sum / dv[u * (u + 1) / 2 + u];
+              for (int w = 0; w < u; ++w) sum -= widen<TA>(dr[u * (u + 1) / 2 + w]) * xs[w][cc];
+              xs[u][cc] = sum / widen<TA>(dr[u * (u + 1) / 2 + u]);
             }
           }
         } else {
@@ -257,11 +271,11 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
           for (int uu = kSmax - 1; uu >= 0; --uu) {
             if (uu < sz) {
               const int base = uu * kSmax - uu * (uu - 1) / 2;  // (uu, uu) in the upper storage
-              TA sum = bv[uu][cc] - acc[uu][cc];
+              TA sum = (TA)br[uu][cc] - acc[uu][cc];
 #pragma unroll
               for (int w = uu + 1; w < kSmax; ++w)
-                if (w < sz) sum -= dv[base + (w - uu)] * xs[w][cc];
-              xs[uu][cc] = sum / dv[base];
+                if (w < sz) sum -= widen<TA>(dr[base + (w - uu)]) * xs[w][cc];
+              xs[uu][cc] = sum / widen<TA>(dr[base]);
             }
           }
         }

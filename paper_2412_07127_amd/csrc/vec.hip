@@ -102,11 +102,12 @@ __global__ __launch_bounds__(kBlock) void k_zero_x(int64_t n, double *__restrict
   }
 }
 
-// -------------------------------------------------------------- r^T z
+// ------------------------------------------------------- r^T z and p^T w
 
+// Per-column dot of two n x R blocks into block partials.
 template <int R, typename TZ>
-__global__ __launch_bounds__(kBlock) void k_dot_rz(int64_t n, const double *__restrict__ r, const TZ *__restrict__ z,
-                                                   double *partials, const SolveFlags *flags) {
+__global__ __launch_bounds__(kBlock) void k_col_dot(int64_t n, const double *__restrict__ r, const TZ *__restrict__ z,
+                                                    double *partials, const SolveFlags *flags) {
   if (flags->n_active == 0) return;
   __shared__ double smem[kRedBlock];
   double acc = 0.0;
@@ -364,10 +365,10 @@ int pcg_dot_rz(int64_t n, int R, const double *r, const void *z, bool f32, doubl
                SolveFlags *flags, hipStream_t s) {
   const unsigned g = vec_grid(n, R);
   if (f32) {
-    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_dot_rz<RR, float>), dim3(g), dim3(kBlock), 0, s, n, r, (const float *)z,
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_col_dot<RR, float>), dim3(g), dim3(kBlock), 0, s, n, r, (const float *)z,
                                          partials, flags));
   } else {
-    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_dot_rz<RR, double>), dim3(g), dim3(kBlock), 0, s, n, r,
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_col_dot<RR, double>), dim3(g), dim3(kBlock), 0, s, n, r,
                                          (const double *)z, partials, flags));
   }
   ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_rz_fin<RR>, dim3(1), dim3(kBlock), 0, s, partials, (int)g, cols, flags));
@@ -393,6 +394,14 @@ int pcg_pw_finalize(int R, const double *partials, int nb, ColState *cols, const
   ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_pw_fin<RR>, dim3(1), dim3(kBlock), 0, s, partials, nb, cols, flags));
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
+}
+
+int pcg_dot_pw(int64_t n, int R, const double *p, const double *w, double *partials, ColState *cols,
+               const SolveFlags *flags, hipStream_t s) {
+  const unsigned g = vec_grid(n, R);
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_col_dot<RR, double>), dim3(g), dim3(kBlock), 0, s, n, p, w, partials, flags));
+  ICPCG_HIP_TRY(hipGetLastError());
+  return pcg_pw_finalize(R, partials, (int)g, cols, flags, s);
 }
 
 int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const double *w, double *partials,
