@@ -72,6 +72,61 @@ def test_grouped_spmv(ctx, key, R):
         assert np.abs(W[:, c] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
 
 
+def long_and_empty_rows(n=700, seed=11, with_diag=False):
+    """General CSR with rows longer than any prefetch window (~230 entries),
+    short rows and, unless with_diag, empty rows (first, last and inside)."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for i in range(n):
+        if not with_diag and i in (0, 5, 6, n // 2, n - 1):
+            rows.append(np.zeros(0, np.int64))
+            continue
+        k = 230 if i % 97 == 3 else int(rng.integers(1, 9))
+        c = set(rng.choice(n, size=k, replace=False).tolist())
+        if with_diag:
+            c.add(i)
+        rows.append(np.array(sorted(c), np.int64))
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    return rp, ci, rng.standard_normal(len(ci))
+
+
+@pytest.mark.parametrize("R", [1, 2, 4, 8, 16])
+def test_spmv_long_and_empty_rows(ctx, R):
+    """Plain SpMV on a raw CSR: empty rows give 0, rows past the prefetch
+    window take the remainder loop."""
+    A = long_and_empty_rows()
+    n = A[0].shape[0] - 1
+    X = np.random.default_rng(R + 7).standard_normal((n, R))
+    W = ctx.spmv(to_gpu(A), torch.from_numpy(X).cuda()).cpu().numpy()
+    for c in range(R):
+        ref = oracle.spmv(*A, X[:, c])
+        assert np.abs(W[:, c] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+    assert np.all(W[[0, 5, 6, n // 2, n - 1]] == 0.0)
+
+
+@pytest.mark.parametrize("R", [1, 4, 16])
+def test_grouped_spmv_long_groups(ctx, R):
+    """Row groups of 3 rows sharing ~150 columns (past the 96-entry window)."""
+    rng = np.random.default_rng(3)
+    n, rows = 450, []
+    for g in range(0, n, 3):
+        k = 150 if g % 30 == 0 else int(rng.integers(1, 20))
+        c = np.array(sorted(set(rng.choice(n, size=k, replace=False).tolist()) | {g, g + 1, g + 2}), np.int64)
+        rows += [c, c, c]
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    A = (rp, ci, rng.standard_normal(len(ci)))
+    M = ctx.matrix(to_gpu(A))
+    X = np.random.default_rng(R).standard_normal((n, R))
+    W = M.spmv(torch.from_numpy(X).cuda()).cpu().numpy()
+    for c in range(R):
+        ref = oracle.spmv(*A, X[:, c])
+        assert np.abs(W[:, c] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+
+
 def test_solve_with_analyzed_matrix(ctx):
     prob, b = workload_problem("q1_8")
     Ah = (prob.row_ptr, prob.col, prob.val)
@@ -159,6 +214,42 @@ def test_trsv_f64(ctx, key, R):
     n = L[0].shape[0] - 1
     P = ctx.prec(to_gpu(L), "f64")
     Rh = np.random.default_rng(R + 1).standard_normal((n, R))
+    Y = P.trsv(torch.from_numpy(Rh).cuda()).cpu().numpy()
+    Z = P.trsv(torch.from_numpy(Y).cuda(), transpose=True).cpu().numpy()
+    for c in range(R):
+        y = oracle.trsv_lower(*L, Rh[:, c])
+        z = oracle.trsv_upper(*U, y)
+        assert relerr(Y[:, c], y) <= 1e-12
+        assert relerr(Z[:, c], z) <= 1e-12
+
+
+def arrow_lower(n=700, dense_from=600, seed=9):
+    """Lower factor whose last rows are dense (every third column): rows of the
+    forward solve and, through them, rows of the backward solve run past the
+    prefetch window."""
+    rng = np.random.default_rng(seed)
+    rows, vals = [], []
+    for i in range(n):
+        if i >= dense_from:
+            c = np.arange(0, i, 3)
+        else:
+            k = min(i, int(rng.integers(0, 5)))
+            c = np.sort(rng.choice(i, size=k, replace=False)) if k else np.zeros(0, int)
+        rows.append(np.concatenate([c, [i]]).astype(np.int64))
+        vals.append(np.concatenate([0.02 * rng.standard_normal(len(c)), [1.0 + rng.random()]]))
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    return rp, np.concatenate(rows).astype(np.int32), np.concatenate(vals)
+
+
+@pytest.mark.parametrize("R", [1, 4, 16])
+def test_trsv_rows_past_window(ctx, R):
+    L = arrow_lower()
+    U = oracle.transpose(*L)
+    assert np.diff(L[0]).max() > 64 and np.diff(U[0]).max() > 64
+    n = L[0].shape[0] - 1
+    P = ctx.prec(to_gpu(L), "f64")
+    Rh = np.random.default_rng(R + 3).standard_normal((n, R))
     Y = P.trsv(torch.from_numpy(Rh).cuda()).cpu().numpy()
     Z = P.trsv(torch.from_numpy(Y).cuda(), transpose=True).cpu().numpy()
     for c in range(R):
