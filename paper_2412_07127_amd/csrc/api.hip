@@ -525,7 +525,7 @@ struct PassBuffers {
   int64_t ngroups;
 };
 
-// w = A x (optionally with the fused p^T w reduction) through the row-group
+// w = A x (optionally with p^T w and alpha) through the row-group
 // kernel when groups are available.
 int spmv_pass(const icpcg_csr *A, const PassBuffers &b, const double *x, double *y, int R, hipStream_t s,
               double *partials = nullptr, ColState *cols = nullptr, const int *active = nullptr) {

@@ -245,8 +245,9 @@ int adam_step(double *th, const double *g, double *m, double *v, int64_t count, 
               double b2, double eps, hipStream_t s);
 int spmv_default_slots(int R);
 
-// partials/cols non-null: fused p^T w reduction and alpha update (active must
-// then point at the solve's SolveFlags); active (nullable) as for trsv.
+// partials/cols non-null: also p^T w and the alpha update, fused into the row
+// kernel (active must then point at the solve's SolveFlags); active (nullable)
+// as for trsv.
 int spmv(const int64_t *rp, const int32_t *ci, const double *v, int64_t n, const double *x,
          double *y, int R, int slots, hipStream_t s, double *partials = nullptr,
          ColState *cols = nullptr, const int *active = nullptr);

@@ -136,9 +136,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t *__restrict__ rp,
 // 0. Every group has a column and finite values (each row stores its
 // diagonal, checked when the matrix handle is made), and that column is one
 // of the group's own, so a non-finite x there makes the rows non-finite
-// either way. The fused p^T w of the solver is a separate pass over p and w
-// (below): keeping p of each row for it inside this kernel costs more
-// registers than the pass costs time.
+// either way. The solver's p^T w is a separate pass over p and w (below):
+// keeping p of each row for it inside this kernel costs more registers than
+// the pass costs time.
 template <int SLOTS> struct GrpDepth {
   static constexpr int v = (88 + SLOTS - 1) / SLOTS > 11 ? 11 : (88 + SLOTS - 1) / SLOTS;
 };

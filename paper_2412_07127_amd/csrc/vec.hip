@@ -5,7 +5,8 @@
 //   init          r = b - A x0, ||b||^2, ||r||^2           -> tolerance, start flags
 //   dot_rz        r^T z                                     -> beta = r_k^T z_k / r_{k-1}^T z_{k-1}
 //   update_p      p = z + beta p (also re-arms y, z as pending for the next solves)
-//   (spmv)        p^T w                                     -> alpha = r^T z / p^T w
+//   dot_pw        p^T w, after the SpMV (fused in the plain
+//                 row kernel)                               -> alpha = r^T z / p^T w
 //   update_xr     x += alpha p, r -= alpha w, ||r||^2        -> iteration count, stop test
 //   true_residual b - A x, ||b - A x||^2                     -> accept / replace / give up
 // Converged or failed columns are frozen (their x, r, p are no longer touched).
