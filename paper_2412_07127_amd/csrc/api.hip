@@ -536,7 +536,8 @@ int spmv_pass(const icpcg_csr *A, const PassBuffers &b, const double *x, double 
 }
 
 // `count` PCG steps of supplementary Algorithm 1 on stream s: z = L^-T L^-1 r,
-// r'z and beta, p = z + beta p, w = A p with p'w, then alpha, x, r and ||r||.
+// r'z and beta (formed by the backward solve for FP32 / BF16 factors on several
+// columns), p = z + beta p, w = A p with p'w, then alpha, x, r and ||r||.
 // Queued steps return at once when no column is active.
 int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const PassBuffers &b, int R,
                   int64_t max_iter, int count, hipStream_t s) {
@@ -553,9 +554,13 @@ int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const
         return st;
     } else {
       if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err, act))) return st;
-      if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err, act))) return st;
+      // the backward solve also forms r^T z and beta where that pays
+      const RzDot rz = trsv_fuses_rz(P, R) ? RzDot{b.r, b.partials, b.cols, fl} : RzDot{};
+      if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err, act, rz))) return st;
     }
-    if ((st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, b.cols, fl, s))) return st;
+    if (!(P->kind == ICPCG_PREC_FACTOR && trsv_fuses_rz(P, R)) &&
+        (st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, b.cols, fl, s)))
+      return st;
     if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.z, b.cols, fl, s))) return st;
     if ((st = spmv_pass(A, b, b.p, b.w, R, s, b.partials, b.cols, act))) return st;
     if ((st = pcg_update_xr(n, R, b.X, b.r, b.p, b.w, b.partials, b.cols, max_iter, fl, s))) return st;

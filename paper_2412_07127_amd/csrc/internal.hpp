@@ -261,8 +261,19 @@ int spmv_grouped_default_slots(int R);
 
 // active (nullable): the solve's count of iterating columns; when it reads 0
 // the launch returns at once (steps queued past convergence cost a launch).
+// rz.partials (nullable, backward solves of a PCG step): also r^T z of every
+// column with r = rz.r (n x R, FP64), folded into beta by k_rz_fin.
+struct RzDot {
+  const double *r = nullptr;
+  double *partials = nullptr;
+  ColState *cols = nullptr;
+  SolveFlags *flags = nullptr;
+};
 int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *out, int R,
-         int64_t ld, hipStream_t s, const Device &dev, int *err, const int *active = nullptr);
+         int64_t ld, hipStream_t s, const Device &dev, int *err, const int *active = nullptr,
+         const RzDot &rz = RzDot{});
+// whether the backward solve of a PCG step with this factor and width forms r^T z
+bool trsv_fuses_rz(const icpcg_prec *P, int R);
 
 int prec_dL(const icpcg_prec *P, const void *Z, const void *Yb, const void *Rb, const void *Y,
             void *dL, int R, hipStream_t s);
@@ -281,6 +292,7 @@ int pcg_pw_finalize(int R, const double *partials, int nb, ColState *cols, const
                     hipStream_t s);
 int pcg_dot_pw(int64_t n, int R, const double *p, const double *w, double *partials, ColState *cols,
                const SolveFlags *flags, hipStream_t s);
+int pcg_rz_finalize(int R, const double *partials, int nb, ColState *cols, SolveFlags *flags, hipStream_t s);
 int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const double *w,
                   double *partials, ColState *cols, int64_t max_iter, SolveFlags *flags,
                   hipStream_t s);

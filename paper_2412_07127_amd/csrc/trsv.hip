@@ -32,7 +32,7 @@
 //    Partial sums meet in a fixed butterfly (deterministic).
 //  * Factor values may be FP64, FP32 or bfloat16 (widened to FP32); FP32 and
 //    bfloat16 factors run FP32 arithmetic.
-#include "internal.hpp"
+#include "reduce.hpp"
 
 namespace icpcg {
 
@@ -94,11 +94,16 @@ __device__ __forceinline__ void publish_elems(TA *p, const TA (&x)[CPL]) {
   }
 }
 
-template <typename TV, typename TA, typename TR, int R, bool UPPER, int QD, int CPL>
+// RZ (backward solves inside the PCG loop): also r^T z of every column, from
+// the residual rows loaded with the right-hand side and each published row,
+// into block partials (a fixed per-lane order over the lane's items, then the
+// block tree).
+template <typename TV, typename TA, typename TR, int R, bool UPPER, int QD, int CPL, bool RZ>
 __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci, const TV *__restrict__ val,
                                                  const SnItem *__restrict__ sched, int64_t nsn,
                                                  const TR *__restrict__ rhs, TA *out, int *err, long long limit,
-                                                 const int *__restrict__ active) {
+                                                 const int *__restrict__ active, const double *__restrict__ rres,
+                                                 double *rz_partials) {
   if (active && *active == 0) return;  // every column of the solve has stopped
   using U = typename Flag<TA>::U;
   constexpr int LPR = R / CPL;                   // lanes per gathered row
@@ -108,6 +113,9 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
   const int lane = threadIdx.x & 63, slot = lane / LPR, c0 = (lane % LPR) * CPL;
   const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
   const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
+  double dot[CPL];
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) dot[cc] = 0.0;
   SnItem nxt;
   if (w0 < nsn) nxt = sched[w0];
   for (int64_t t = w0; t < nsn; t += nw) {
@@ -165,6 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
     TR br[kSmax][CPL];
     TA dv[NDB];
     TA bv[kSmax][CPL];
+    double rr[kSmax][CPL];  // residual rows (RZ)
     if constexpr (kRaw) {
 #pragma unroll
       for (int u = 0; u < kSmax; ++u) {
@@ -179,6 +188,10 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
         }
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) br[u][cc] = rhs[(int64_t)(a + uc) * R + c0 + cc];
+        if constexpr (RZ) {
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc) rr[u][cc] = rres[(int64_t)(a + uc) * R + c0 + cc];
+        }
       }
     } else if (slot == 0) {
 #pragma unroll
@@ -193,6 +206,10 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
         }
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) bv[u][cc] = u < sz ? (TA)rhs[(int64_t)(a + u) * R + c0 + cc] : TA(0);
+        if constexpr (RZ) {
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc) rr[u][cc] = u < sz ? rres[(int64_t)(a + u) * R + c0 + cc] : 0.0;
+        }
       }
     }
     auto dval = [&](int i) -> TA {
@@ -324,7 +341,19 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
 #pragma unroll
       for (int u = 0; u < kSmax; ++u)
         if (u < sz) publish_elems<TA, CPL>(out + (int64_t)(a + u) * R + c0, xs[u]);
+      if constexpr (RZ) {
+#pragma unroll
+        for (int u = 0; u < kSmax; ++u)
+          if (u < sz) {
+#pragma unroll
+            for (int cc = 0; cc < CPL; ++cc) dot[cc] += rr[u][cc] * (double)xs[u][cc];
+          }
+      }
     }
+  }
+  if constexpr (RZ) {
+    __shared__ double smem[CPL * kRedBlock];
+    block_partials_cpl<R, CPL>(dot, rz_partials, smem);
   }
 }
 
@@ -362,31 +391,36 @@ template <typename TA, int R> struct Depth {
   static constexpr int v = (40 + slots - 1) / slots;
 };
 
-template <typename TV, typename TA, typename TR, int R, bool UPPER>
+template <typename TV, typename TA, typename TR, int R, bool UPPER, bool RZ>
 int launch(const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs, TA *out, hipStream_t s,
-           const Device &dev, int *err, const int *active) {
+           const Device &dev, int *err, const int *active, const RzDot &rz) {
+  if constexpr (RZ && R == 1) {  // not fused at one column (trsv_fuses_rz)
+    return ICPCG_E_INVALID;
+  } else {
   if (S.nsn == 0) return ICPCG_OK;
-  auto k = k_trsv<TV, TA, TR, R, UPPER, Depth<TA, R>::v, Cpl<TA, R>::v>;
+  auto k = k_trsv<TV, TA, TR, R, UPPER, Depth<TA, R>::v, Cpl<TA, R>::v, RZ>;
   static int per_cu = 0;  // occupancy of this instantiation (same on every MI355X)
   int64_t grid = resident_blocks(k, dev, per_cu);
   const int64_t need = (S.nsn + 3) / 4;
   if (need < grid) grid = need;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kBlock), 0, s, ci, val, S.items.as<SnItem>(), S.nsn, rhs, out,
-                     err, dev.wait_ticks, active);
+                     err, dev.wait_ticks, active, rz.r, rz.partials);
   ICPCG_HIP_TRY(hipGetLastError());
+  if constexpr (RZ) return pcg_rz_finalize(R, rz.partials, (int)grid, rz.cols, rz.flags, s);
   return ICPCG_OK;
+  }
 }
 
-template <typename TV, typename TA, typename TR, bool UPPER>
+template <typename TV, typename TA, typename TR, bool UPPER, bool RZ = false>
 int dispatch_r(int R, const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs, TA *out, hipStream_t s,
-               const Device &dev, int *err, const int *active) {
+               const Device &dev, int *err, const int *active, const RzDot &rz = RzDot{}) {
   switch (R) {
-    case 1: return launch<TV, TA, TR, 1, UPPER>(S, ci, val, rhs, out, s, dev, err, active);
-    case 2: return launch<TV, TA, TR, 2, UPPER>(S, ci, val, rhs, out, s, dev, err, active);
-    case 4: return launch<TV, TA, TR, 4, UPPER>(S, ci, val, rhs, out, s, dev, err, active);
-    case 8: return launch<TV, TA, TR, 8, UPPER>(S, ci, val, rhs, out, s, dev, err, active);
-    case 16: return launch<TV, TA, TR, 16, UPPER>(S, ci, val, rhs, out, s, dev, err, active);
+    case 1: return launch<TV, TA, TR, 1, UPPER, RZ>(S, ci, val, rhs, out, s, dev, err, active, rz);
+    case 2: return launch<TV, TA, TR, 2, UPPER, RZ>(S, ci, val, rhs, out, s, dev, err, active, rz);
+    case 4: return launch<TV, TA, TR, 4, UPPER, RZ>(S, ci, val, rhs, out, s, dev, err, active, rz);
+    case 8: return launch<TV, TA, TR, 8, UPPER, RZ>(S, ci, val, rhs, out, s, dev, err, active, rz);
+    case 16: return launch<TV, TA, TR, 16, UPPER, RZ>(S, ci, val, rhs, out, s, dev, err, active, rz);
     default:
       set_error("trsv: unsupported block width " + std::to_string(R));
       return ICPCG_E_INVALID;
@@ -395,11 +429,31 @@ int dispatch_r(int R, const TriSchedule &S, const int32_t *ci, const TV *val, co
 
 }  // namespace
 
+// The fused r^T z costs registers: FP64 solves would lose resident waves
+// (16 columns: 3 -> 2 per SIMD; one column: 7 -> 5) and one-column solves are
+// bound by their dependency depth, so those keep the separate pass (about 10 us
+// at one column), while FP32 arithmetic on 2-16 columns saves its pass over r
+// and z (about 0.1 ms at 16 columns) at no cost in waves.
+bool trsv_fuses_rz(const icpcg_prec *P, int R) { return P->dtype != ICPCG_F64 && R > 1; }
+
 // `out` must hold the pending pattern in every entry on entry.
 int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *out, int R, int64_t, hipStream_t s,
-         const Device &dev, int *err, const int *active) {
+         const Device &dev, int *err, const int *active, const RzDot &rz) {
   const int32_t *ci = upper ? P->uci.as<int32_t>() : P->lci.as<int32_t>();
   const TriSchedule &S = upper ? P->su : P->sl;
+  if (rz.partials) {
+    // the backward solve of a PCG step (right-hand side in the factor's precision)
+    if (!upper || rhs_f64 || !trsv_fuses_rz(P, R)) {
+      set_error("trsv: r^T z only with the backward solve of a PCG step (FP32 or BF16 factor, 2-16 columns)");
+      return ICPCG_E_INVALID;
+    }
+    if (P->dtype == ICPCG_F32)
+      return dispatch_r<float, float, float, true, true>(R, S, ci, P->uval_lo.as<float>(), (const float *)rhs,
+                                                         (float *)out, s, dev, err, active, rz);
+    return dispatch_r<unsigned short, float, float, true, true>(R, S, ci, P->uval_lo.as<unsigned short>(),
+                                                                (const float *)rhs, (float *)out, s, dev, err,
+                                                                active, rz);
+  }
   if (P->dtype == ICPCG_F64) {
     const double *v = upper ? P->uval.as<double>() : P->lval.as<double>();
     if (upper)

@@ -377,6 +377,12 @@ int pcg_dot_rz(int64_t n, int R, const double *r, const void *z, bool f32, doubl
   return ICPCG_OK;
 }
 
+int pcg_rz_finalize(int R, const double *partials, int nb, ColState *cols, SolveFlags *flags, hipStream_t s) {
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_rz_fin<RR>, dim3(1), dim3(kBlock), 0, s, partials, nb, cols, flags));
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
 int pcg_update_p(int64_t n, int R, const void *z, bool f32, double *p, void *y, void *zf, const ColState *cols,
                  const SolveFlags *flags, hipStream_t s) {
   const unsigned g = vec_grid(n, R);
