@@ -3,7 +3,9 @@
 // writes per-block partials plus a one-block finalize kernel that folds them in
 // fixed order and updates the per-column state:
 //   init          r = b - A x0, ||b||^2, ||r||^2           -> tolerance, start flags
-//   dot_rz        r^T z                                     -> beta = r_k^T z_k / r_{k-1}^T z_{k-1}
+//   dot_rz        r^T z (formed by the backward triangular
+//                 solve for FP32 / BF16 factors on several
+//                 columns, k_rz_fin alone then)             -> beta = r_k^T z_k / r_{k-1}^T z_{k-1}
 //   update_p      p = z + beta p (also re-arms y, z as pending for the next solves)
 //   dot_pw        p^T w, after the SpMV (fused in the plain
 //                 row kernel)                               -> alpha = r^T z / p^T w
