@@ -561,7 +561,7 @@ int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const
     if (!(P->kind == ICPCG_PREC_FACTOR && trsv_fuses_rz(P, R)) &&
         (st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, b.cols, fl, s)))
       return st;
-    if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.z, b.cols, fl, s))) return st;
+    if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.cols, fl, s))) return st;
     if ((st = spmv_pass(A, b, b.p, b.w, R, s, b.partials, b.cols, act))) return st;
     if ((st = pcg_update_xr(n, R, b.X, b.r, b.p, b.w, b.partials, b.cols, max_iter, fl, s))) return st;
   }

@@ -286,8 +286,9 @@ int pcg_init(int64_t n, int R, const double *B, const double *W, double *r, doub
 int pcg_zero_x(int64_t n, int R, double *X, const ColState *cols, hipStream_t s);
 int pcg_dot_rz(int64_t n, int R, const double *r, const void *z, bool f32, double *partials,
                ColState *cols, SolveFlags *flags, hipStream_t s);
-int pcg_update_p(int64_t n, int R, const void *z, bool f32, double *p, void *y, void *zf,
-                 const ColState *cols, const SolveFlags *flags, hipStream_t s);
+// p = z + beta p; then y and z (read in place) are re-armed as pending
+int pcg_update_p(int64_t n, int R, void *z, bool f32, double *p, void *y, const ColState *cols,
+                 const SolveFlags *flags, hipStream_t s);
 int pcg_pw_finalize(int R, const double *partials, int nb, ColState *cols, const SolveFlags *flags,
                     hipStream_t s);
 int pcg_dot_pw(int64_t n, int R, const double *p, const double *w, double *partials, ColState *cols,

@@ -145,9 +145,10 @@ __global__ __launch_bounds__(kBlock) void k_rz_fin(const double *partials, int n
 
 // ------------------------------------------------------------- update p
 
+// z is read and then re-armed as pending in place (one pointer, so the
+// compiler keeps each read before the store to the same element).
 template <int R, typename TZ>
-__global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, const TZ *__restrict__ z, double *__restrict__ p,
-                                                     TZ *__restrict__ y, TZ *__restrict__ zf,
+__global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, TZ *z, double *__restrict__ p, TZ *__restrict__ y,
                                                      const ColState *__restrict__ cols, const SolveFlags *flags) {
   if (flags->n_active == 0) return;
   __shared__ double beta[R];
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, const TZ *__rest
     const int c = (int)(e % R);
     if (act[c]) p[e] = (double)z[e] + beta[c] * p[e];
     y[e] = Pending<TZ>::get();
-    zf[e] = Pending<TZ>::get();
+    z[e] = Pending<TZ>::get();
   }
 }
 
@@ -385,15 +386,15 @@ int pcg_rz_finalize(int R, const double *partials, int nb, ColState *cols, Solve
   return ICPCG_OK;
 }
 
-int pcg_update_p(int64_t n, int R, const void *z, bool f32, double *p, void *y, void *zf, const ColState *cols,
+int pcg_update_p(int64_t n, int R, void *z, bool f32, double *p, void *y, const ColState *cols,
                  const SolveFlags *flags, hipStream_t s) {
   const unsigned g = vec_grid(n, R);
   if (f32) {
-    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, float>), dim3(g), dim3(kBlock), 0, s, n, (const float *)z, p,
-                                         (float *)y, (float *)zf, cols, flags));
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, float>), dim3(g), dim3(kBlock), 0, s, n, (float *)z, p,
+                                         (float *)y, cols, flags));
   } else {
-    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, double>), dim3(g), dim3(kBlock), 0, s, n, (const double *)z,
-                                         p, (double *)y, (double *)zf, cols, flags));
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, double>), dim3(g), dim3(kBlock), 0, s, n, (double *)z, p,
+                                         (double *)y, cols, flags));
   }
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
