@@ -179,3 +179,68 @@ def test_adam_closed_form_first_step():
     gr = np.array([3.0, -0.25, 1e-3])
     t1, m, v = G.adam_step(th, gr, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=0.0)
     assert np.allclose(t1, th - 0.01 * np.sign(gr), rtol=1e-15)
+
+
+def test_edge_scale_closed_form_and_dense_brute_force():
+    """The edge input scale s is the population standard deviation of the stored
+    entries of tril(A) (the edges, diagonal included). Tridiagonal 2/-1 of order
+    m: m entries 2 and m-1 entries -1, so with N = 2m-1 the mean is
+    (m+1)/N and the variance (m (2-mu)^2 + (m-1)(1+mu)^2) / N. Dense case:
+    every lower entry of a random SPD matrix, summed by plain loops. Full A
+    instead of tril(A), or the sample (N-1) variance, differs in both."""
+    for m in (3, 10, 41):
+        T = 2 * np.eye(m) - np.eye(m, k=1) - np.eye(m, k=-1)
+        A = dense_to_csr(T)
+        st, L, *_ = oracle.ic0_shifted(*A)
+        g = G.Graph(A, L)
+        N = 2 * m - 1
+        mu = (m + 1) / N
+        var = (m * (2 - mu) ** 2 + (m - 1) * (1 + mu) ** 2) / N
+        assert G.edge_scale(g) == pytest.approx(np.sqrt(var), rel=1e-14)
+    rng = np.random.default_rng(11)
+    n = 9
+    Mx = rng.standard_normal((n, n))
+    D = Mx @ Mx.T + n * np.eye(n)
+    A = dense_to_csr(D, np.ones((n, n), bool))
+    st, L, *_ = oracle.ic0_shifted(*A)
+    g = G.Graph(A, L)
+    vals = [D[i, j] for i in range(n) for j in range(i + 1)]
+    mean = sum(vals) / len(vals)
+    var = sum((v - mean) ** 2 for v in vals) / len(vals)
+    assert G.edge_scale(g) == pytest.approx(var ** 0.5, rel=1e-13)
+
+
+def test_corrected_factor_scale_equivariance():
+    """Eq. 2 corrects the factor in the units of the scaled matrix A / s that the
+    network sees: every input of the network is invariant under A -> c A (ratios,
+    degrees, a_ij / s), L_IC(c A) = sqrt(c) L_IC(A) and s(c A) = c s(A), so the
+    corrected factor must scale by sqrt(c) as a factor of c A does. With c = 4
+    every step scales by a power of two, so the identity is exact."""
+    p = q1_elasticity(2, 1.0, 5)
+    th = G.init_params(3, zero_output=False)
+    outs = []
+    for c in (1.0, 4.0, 3.0):
+        A = (p.row_ptr, p.col, p.val * c)
+        st, L, *_ = oracle.ic0_shifted(*A)
+        g = G.Graph(A, L)
+        outs.append(G.predict(g, th))
+    assert np.array_equal(outs[1], 2.0 * outs[0])
+    assert np.allclose(outs[2], np.sqrt(3.0) * outs[0], rtol=1e-12, atol=0)
+    assert not np.array_equal(outs[0], G.predict(G.Graph((p.row_ptr, p.col, p.val), oracle.ic0_shifted(
+        p.row_ptr, p.col, p.val)[1]), G.init_params(3, zero_output=True)))
+
+
+def test_corrected_factor_constant_output_diagonal():
+    """A network whose last edge layer outputs the constant c on every edge: on
+    the diagonal the corrected squared pivot is the IC(0) squared pivot times
+    exp(c) (the exponential, then the square root, of the correction), and off
+    the diagonal the change is the same for every entry."""
+    A, L, g = small_graph()
+    d = G.unpack(G.init_params(4, zero_output=True).copy())
+    c = 0.3
+    d["e2_b2"][0] = c
+    Lp = G.predict(g, G.pack(d))
+    dg = g.diag
+    assert np.allclose((Lp[dg] / g.Lic[dg]) ** 2, np.exp(c), rtol=1e-14, atol=0)
+    off = Lp[~dg] - g.Lic[~dg]
+    assert np.allclose(off, off[0], rtol=1e-12, atol=0) and off[0] > 0

@@ -533,3 +533,81 @@ def test_dropout_of_ic_factor_is_a_subpattern():
         off = ~np.eye(n, dtype=bool)
         assert np.array_equal(np.diag(D), np.diag(F))
         assert np.array_equal(D[off], np.where(np.abs(F) > eps, F, 0.0)[off])
+
+
+# ------------------------------------------------- residual replacement
+
+def _offset_case(n, max_replace):
+    """A = I_n, L = I_n, b = 3/4 per entry, x_0 = 2^53 per entry. Every step is
+    exact or rounds by hand: r_0 = fl(3/4 - 2^53) = -(2^53 - 1), so z = p = r_0,
+    alpha = r_0^T z / p^T A p = 1 and x_1 = 2^53 + r_0 = 1 exactly, while the
+    recurrence gives r_1 = r_0 - r_0 = 0: the recurrence has converged but the
+    true residual b - x_1 = -1/4 per entry (relative 1/3). A replacement sets
+    r = -1/4; then beta = (n/16) / fl(n (2^53 - 1)^2) ~ 2^-110 leaves
+    p = fl(-1/4 + beta r_0... ) = -1/4 (the term is below half an ulp of 1/4),
+    alpha = 1 and x_2 = 1 - 1/4 = 3/4 exactly, r_2 = 0 and b - x_2 = 0."""
+    L, U = _identity_factor(n)
+    A = csr_of(np.eye(n))
+    b = np.full(n, 0.75)
+    x0 = np.full(n, 2.0 ** 53)
+    return oracle.pcg(A, L, U, b, x0=x0, rtol=1e-8, max_replace=max_replace, max_iter=50)
+
+
+@pytest.mark.parametrize("n", [1, 4])
+def test_pcg_replacement_worked_example(n):
+    """Supplementary Algorithm 1 with the true-residual check: a recurrence that
+    reaches zero while b - A x does not triggers exactly one replacement, after
+    which one more step lands on the exact solution."""
+    res = _offset_case(n, 0)
+    # no replacement allowed: the recurrence stopped after 1 product, x_1 = 1
+    assert res["status"] == oracle.TRUE_RESIDUAL
+    assert res["iters"] == 1 and res["replacements"] == 0
+    assert np.all(res["x"] == 1.0)
+    assert res["relres"] == 0.0 and res["true_relres"] == pytest.approx(1.0 / 3.0, rel=1e-15)
+    for mr in (1, 3):
+        res = _offset_case(n, mr)
+        assert res["status"] == oracle.OK
+        assert res["iters"] == 2 and res["replacements"] == 1
+        assert np.all(res["x"] == 0.75)
+        assert res["true_relres"] == 0.0
+
+
+def test_pcg_replacement_counts_against_max_iter():
+    """A replacement at the iteration cap reports the cap, not success."""
+    L, U = _identity_factor(2)
+    res = oracle.pcg(csr_of(np.eye(2)), L, U, np.full(2, 0.75), x0=np.full(2, 2.0 ** 53), rtol=1e-8,
+                     max_replace=3, max_iter=1)
+    assert res["status"] == oracle.MAXITER
+    assert res["iters"] == 1 and res["replacements"] == 1
+    assert np.all(res["x"] == 1.0)
+
+
+def test_pcg_replacement_below_attainable_accuracy():
+    """A tolerance below what FP64 attains in b - A x on the 8^3 workload
+    (about 2e-14 here): the recurrence residual keeps shrinking past it, the
+    true residual does not, so each allowed replacement is used and the status
+    says the true residual stayed above the tolerance. A replacement restarts
+    the recurrence from b - A x, so the run is longer and its recurrence
+    residual again ends below the tolerance. (With three replacements the
+    restarted recurrences wander for hundreds of iterations and their length
+    changes with the last bits of the input, so the pin stops at one.)"""
+    prob, b = build_workload("q1_8")
+    A = (prob.row_ptr, prob.col, prob.val)
+    st, L, alpha, _, _ = oracle.ic0_shifted(*A)
+    U = oracle.transpose(*L)
+    D = prob.to_scipy().toarray()
+    nb = np.linalg.norm(b)
+    eps = np.finfo(float).eps
+    prev = None
+    for mr in (0, 1):
+        res = oracle.pcg(A, L, U, b, rtol=1e-14, max_replace=mr, max_iter=2000)
+        assert res["status"] == oracle.TRUE_RESIDUAL
+        assert res["replacements"] == mr
+        assert res["relres"] <= 1e-14 < res["true_relres"]
+        tr = np.linalg.norm(b - D @ res["x"]) / nb
+        assert tr == pytest.approx(res["true_relres"], rel=1e-2)
+        # the attainable level: a small multiple of eps ||A|| ||x|| / ||b||
+        assert tr <= 100 * eps * np.linalg.norm(D, 2) * np.linalg.norm(res["x"]) / nb
+        if prev is not None:
+            assert res["iters"] > prev
+        prev = res["iters"]
