@@ -49,6 +49,10 @@
  *                            each shift attempt as one sync-free launch
  *                            instead of one launch per level of tril(A) (same
  *                            bits; slower on the elasticity workloads)
+ *   ICPCG_FUSE_RZ            0: the backward solve of a PCG step never forms
+ *                            r^T z itself (a separate pass does, as for FP64
+ *                            factors and one column); default 1 (fused for
+ *                            FP32 / BF16 factors on 2-16 columns)
  *   ICPCG_WAIT_LIMIT_US      time limit of one device-side dependency wait
  *                            (default 4 s); a wait that reaches it gives up,
  *                            the kernel finishes with a NaN in that place and
@@ -239,6 +243,19 @@ icpcg_status icpcg_trsv(icpcg_ctx *ctx, const icpcg_prec *P, int transpose, cons
  * kept for icpcg_apply_backward and may not be NULL. */
 icpcg_status icpcg_apply(icpcg_ctx *ctx, const icpcg_prec *P, const void *R, int r_is_f64,
                          void *Y, void *Z, int64_t nrhs);
+
+/* The preconditioner solve as a PCG step runs it (supplementary Algorithm 1:
+ * the two triangle solves, then r^T z for beta): Y = L^-1 R and Z = L^-T Y
+ * with R an FP64 block, Y and Z in the factor's block type (FP64, or FP32 for
+ * an FP32 / BF16 factor, R rounded to FP32 on load), and rz[k] = sum_i
+ * R_ik Z_ik accumulated in FP64 for every column k (rz: device, nrhs FP64
+ * values). For FP32 / BF16 factors on 2-16 columns the backward solve forms
+ * r^T z from the rows it publishes (the fused form icpcg_solve uses; see
+ * ICPCG_FUSE_RZ); otherwise a separate pass over R and Z does. The sum order
+ * is fixed by the launch shape (deterministic). Uses the context's reduction
+ * workspace; stream-ordered. Errors: ICPCG_E_INVALID, ICPCG_E_NOMEM. */
+icpcg_status icpcg_apply_rz(icpcg_ctx *ctx, const icpcg_prec *P, const double *R, void *Y, void *Z,
+                            double *rz, int64_t nrhs);
 
 /* Reverse-mode derivative of Z = L^-T L^-1 R (not in the paper; what training
  * a learned correction of L needs). Given G = dl/dZ and the Y, Z of the

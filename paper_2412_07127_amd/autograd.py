@@ -20,7 +20,7 @@ class PrecApply(torch.autograd.Function):
         Y, Z = prec.apply(R.detach())
         ctx.save_for_backward(Y, Z)
         ctx.prec = prec
-        ctx.version = prec_version(prec)
+        ctx.version = prec.version
         ctx.l_dtype = l_val.dtype
         ctx.r_dtype = R.dtype
         return Z
@@ -28,14 +28,10 @@ class PrecApply(torch.autograd.Function):
     @staticmethod
     def backward(ctx, G: torch.Tensor):
         Y, Z = ctx.saved_tensors
-        if prec_version(ctx.prec) != ctx.version:
+        if ctx.prec.version != ctx.version:
             raise RuntimeError("the preconditioner's values changed between forward and backward")
         dR, dL = ctx.prec.apply_backward(G, Y, Z)
         return dL.to(ctx.l_dtype), dR.to(ctx.r_dtype), None
-
-
-def prec_version(prec: Preconditioner) -> int:
-    return prec.L.val.data_ptr() ^ (prec.L.val._version << 1)
 
 
 def prec_apply(l_val: torch.Tensor, R: torch.Tensor, prec: Preconditioner) -> torch.Tensor:

@@ -173,6 +173,7 @@ icpcg_status icpcg_create(icpcg_ctx **out, void *stream) {
   }
   if (const char *e = std::getenv("ICPCG_TRSV_WAVES_PER_CU")) ctx->dev.trsv_waves_per_cu = std::atoi(e);
   if (const char *e = std::getenv("ICPCG_IC0_SYNC_FREE")) ctx->dev.ic0_sync_free = std::atoi(e) != 0;
+  if (const char *e = std::getenv("ICPCG_FUSE_RZ")) ctx->dev.fuse_rz = std::atoi(e) != 0;
   if (ensure_flags(ctx) != ICPCG_OK) {
     delete ctx;
     return ICPCG_E_NOMEM;
@@ -490,6 +491,30 @@ icpcg_status icpcg_apply(icpcg_ctx *ctx, const icpcg_prec *P, const void *R, int
   return finish(ctx, trsv(P, true, Y, !lo, Z, (int)nrhs, nrhs, s, ctx->dev, &dev_flags(ctx)->err));
 }
 
+icpcg_status icpcg_apply_rz(icpcg_ctx *ctx, const icpcg_prec *P, const double *R, void *Y, void *Z, double *rz,
+                            int64_t nrhs) {
+  if (!ctx || !P || !R || !Y || !Z || !rz || !pow2_width(nrhs))
+    return fail(ctx, ICPCG_E_INVALID, "apply_rz: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
+  if (not_factor(ctx, P, "apply_rz")) return ICPCG_E_INVALID;
+  const bool lo = P->dtype != ICPCG_F64;
+  hipStream_t s = ctx->stream;
+  Workspace &ws = ctx->ws;
+  if (ws.partials.reserve((size_t)kMaxDotBlocks * nrhs * 2 * 8)) return finish(ctx, ICPCG_E_NOMEM);
+  double *part = ws.partials.as<double>();
+  int *err = &dev_flags(ctx)->err;
+  const int Rw = (int)nrhs;
+  int st;
+  if ((st = fill_pending(Y, P->n * nrhs, lo, s))) return finish(ctx, st);
+  if ((st = trsv(P, false, R, true, Y, Rw, nrhs, s, ctx->dev, err))) return finish(ctx, st);
+  if ((st = fill_pending(Z, P->n * nrhs, lo, s))) return finish(ctx, st);
+  if (trsv_fuses_rz(P, Rw, ctx->dev)) {
+    RzDot d{R, part, nullptr, nullptr, rz};
+    return finish(ctx, trsv(P, true, Y, !lo, Z, Rw, nrhs, s, ctx->dev, err, nullptr, d));
+  }
+  if ((st = trsv(P, true, Y, !lo, Z, Rw, nrhs, s, ctx->dev, err))) return finish(ctx, st);
+  return finish(ctx, col_dot_out(P->n, Rw, R, Z, lo, part, rz, s));
+}
+
 icpcg_status icpcg_apply_backward(icpcg_ctx *ctx, const icpcg_prec *P, const void *G, const void *Y, const void *Z,
                                   void *Ybar, void *dR, void *dL, int64_t nrhs) {
   if (!ctx || !P || !G || !Y || !Z || !Ybar || !dR || !dL || !pow2_width(nrhs))
@@ -555,10 +580,10 @@ int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const
     } else {
       if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err, act))) return st;
       // the backward solve also forms r^T z and beta where that pays
-      const RzDot rz = trsv_fuses_rz(P, R) ? RzDot{b.r, b.partials, b.cols, fl} : RzDot{};
+      const RzDot rz = trsv_fuses_rz(P, R, ctx->dev) ? RzDot{b.r, b.partials, b.cols, fl} : RzDot{};
       if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err, act, rz))) return st;
     }
-    if (!(P->kind == ICPCG_PREC_FACTOR && trsv_fuses_rz(P, R)) &&
+    if (!(P->kind == ICPCG_PREC_FACTOR && trsv_fuses_rz(P, R, ctx->dev)) &&
         (st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, b.cols, fl, s)))
       return st;
     if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.cols, fl, s))) return st;
@@ -642,6 +667,13 @@ int run_pass(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const Pass
       if ((st = spmv_pass(A, b, b.X, b.w, R, s))) return st;
       if ((st = pcg_true_residual(n, R, b.B, b.w, b.partials, b.cols, max_iter, o.max_replace, 0, fl, s))) return st;
       if ((st = pcg_replace_r(n, R, b.w, b.r, b.cols, s))) return st;
+      // The step that stopped the last active column may have ended before its
+      // p update (a breakdown of r^T z), which is where y and z are re-armed for
+      // the next solves: re-arm them here, so a column that a replacement
+      // re-activates never reads an earlier step's values as published.
+      if (P->kind == ICPCG_PREC_FACTOR &&
+          ((st = fill_pending(b.y, n * R, lo, s)) || (st = fill_pending(b.z, n * R, lo, s))))
+        return st;
       continue;
     }
     if (steps > guard) {

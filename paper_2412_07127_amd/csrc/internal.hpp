@@ -50,6 +50,7 @@ struct Device {
   int num_cu = 256;
   int trsv_waves_per_cu = 0;  // 0: as many as fit
   bool ic0_sync_free = false;  // IC(0) in one sync-free launch instead of level launches
+  bool fuse_rz = true;         // backward solves of a PCG step form r^T z where that pays
   long long wall_hz = 100000000;  // wall_clock64 rate
   long long wait_ticks = 400000000;  // device-side wait limit (4 s)
 };
@@ -262,18 +263,20 @@ int spmv_grouped_default_slots(int R);
 // active (nullable): the solve's count of iterating columns; when it reads 0
 // the launch returns at once (steps queued past convergence cost a launch).
 // rz.partials (nullable, backward solves of a PCG step): also r^T z of every
-// column with r = rz.r (n x R, FP64), folded into beta by k_rz_fin.
+// column with r = rz.r (n x R, FP64), folded into beta by k_rz_fin, or, when
+// rz.out is set, into out[c] (FP64, one value per column).
 struct RzDot {
   const double *r = nullptr;
   double *partials = nullptr;
   ColState *cols = nullptr;
   SolveFlags *flags = nullptr;
+  double *out = nullptr;
 };
 int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *out, int R,
          int64_t ld, hipStream_t s, const Device &dev, int *err, const int *active = nullptr,
          const RzDot &rz = RzDot{});
 // whether the backward solve of a PCG step with this factor and width forms r^T z
-bool trsv_fuses_rz(const icpcg_prec *P, int R);
+bool trsv_fuses_rz(const icpcg_prec *P, int R, const Device &dev);
 
 int prec_dL(const icpcg_prec *P, const void *Z, const void *Yb, const void *Rb, const void *Y,
             void *dL, int R, hipStream_t s);
@@ -294,6 +297,11 @@ int pcg_pw_finalize(int R, const double *partials, int nb, ColState *cols, const
 int pcg_dot_pw(int64_t n, int R, const double *p, const double *w, double *partials, ColState *cols,
                const SolveFlags *flags, hipStream_t s);
 int pcg_rz_finalize(int R, const double *partials, int nb, ColState *cols, SolveFlags *flags, hipStream_t s);
+// out[c] = column c's sum of the nb block partials (fixed order)
+int dot_finalize_out(int R, const double *partials, int nb, double *out, hipStream_t s);
+// out[c] = sum_i r[i, c] z[i, c] (FP64; z FP64 or FP32), deterministic
+int col_dot_out(int64_t n, int R, const double *r, const void *z, bool f32, double *partials, double *out,
+                hipStream_t s);
 int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const double *w,
                   double *partials, ColState *cols, int64_t max_iter, SolveFlags *flags,
                   hipStream_t s);

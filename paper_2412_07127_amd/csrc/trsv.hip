@@ -407,7 +407,10 @@ int launch(const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kBlock), 0, s, ci, val, S.items.as<SnItem>(), S.nsn, rhs, out,
                      err, dev.wait_ticks, active, rz.r, rz.partials);
   ICPCG_HIP_TRY(hipGetLastError());
-  if constexpr (RZ) return pcg_rz_finalize(R, rz.partials, (int)grid, rz.cols, rz.flags, s);
+  if constexpr (RZ) {
+    if (rz.out) return dot_finalize_out(R, rz.partials, (int)grid, rz.out, s);
+    return pcg_rz_finalize(R, rz.partials, (int)grid, rz.cols, rz.flags, s);
+  }
   return ICPCG_OK;
   }
 }
@@ -434,7 +437,9 @@ int dispatch_r(int R, const TriSchedule &S, const int32_t *ci, const TV *val, co
 // bound by their dependency depth, so those keep the separate pass (about 10 us
 // at one column), while FP32 arithmetic on 2-16 columns saves its pass over r
 // and z (about 0.1 ms at 16 columns) at no cost in waves.
-bool trsv_fuses_rz(const icpcg_prec *P, int R) { return P->dtype != ICPCG_F64 && R > 1; }
+bool trsv_fuses_rz(const icpcg_prec *P, int R, const Device &dev) {
+  return dev.fuse_rz && P->dtype != ICPCG_F64 && R > 1;
+}
 
 // `out` must hold the pending pattern in every entry on entry.
 int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *out, int R, int64_t, hipStream_t s,
@@ -443,7 +448,7 @@ int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *o
   const TriSchedule &S = upper ? P->su : P->sl;
   if (rz.partials) {
     // the backward solve of a PCG step (right-hand side in the factor's precision)
-    if (!upper || rhs_f64 || !trsv_fuses_rz(P, R)) {
+    if (!upper || rhs_f64 || !trsv_fuses_rz(P, R, dev)) {
       set_error("trsv: r^T z only with the backward solve of a PCG step (FP32 or BF16 factor, 2-16 columns)");
       return ICPCG_E_INVALID;
     }

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_zero_x(int64_t n, double *__restrict
 template <int R, typename TZ>
 __global__ __launch_bounds__(kBlock) void k_col_dot(int64_t n, const double *__restrict__ r, const TZ *__restrict__ z,
                                                     double *partials, const SolveFlags *flags) {
-  if (flags->n_active == 0) return;
+  if (flags && flags->n_active == 0) return;
   __shared__ double smem[kRedBlock];
   double acc = 0.0;
   ICPCG_GRID_LOOP(e, n * R) acc += r[e] * (double)z[e];
@@ -141,6 +141,15 @@ __global__ __launch_bounds__(kBlock) void k_rz_fin(const double *partials, int n
   }
   __syncthreads();
   count_flags<R>(cols, flags);
+}
+
+// Plain per-column sums of block partials (icpcg_apply_rz).
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_dot_out(const double *partials, int nb, double *out) {
+  __shared__ double smem[kRedBlock];
+  __shared__ double res[R];
+  fold_partials<R, 1>(partials, nb, smem, res);
+  if (threadIdx.x < R) out[threadIdx.x] = res[threadIdx.x];
 }
 
 // ------------------------------------------------------------- update p
@@ -384,6 +393,26 @@ int pcg_rz_finalize(int R, const double *partials, int nb, ColState *cols, Solve
   ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_rz_fin<RR>, dim3(1), dim3(kBlock), 0, s, partials, nb, cols, flags));
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
+}
+
+int dot_finalize_out(int R, const double *partials, int nb, double *out, hipStream_t s) {
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_dot_out<RR>, dim3(1), dim3(kBlock), 0, s, partials, nb, out));
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int col_dot_out(int64_t n, int R, const double *r, const void *z, bool f32, double *partials, double *out,
+                hipStream_t s) {
+  const unsigned g = vec_grid(n, R);
+  if (f32) {
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_col_dot<RR, float>), dim3(g), dim3(kBlock), 0, s, n, r, (const float *)z,
+                                         partials, nullptr));
+  } else {
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_col_dot<RR, double>), dim3(g), dim3(kBlock), 0, s, n, r,
+                                         (const double *)z, partials, nullptr));
+  }
+  ICPCG_HIP_TRY(hipGetLastError());
+  return dot_finalize_out(R, partials, (int)g, out, s);
 }
 
 int pcg_update_p(int64_t n, int R, void *z, bool f32, double *p, void *y, const ColState *cols,

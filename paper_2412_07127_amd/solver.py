@@ -309,6 +309,7 @@ class Preconditioner:
         self.ctx, self.h, self.L, self.dtype = ctx, h, Lf, dtype
         self.kind = "factor"
         self._n = Lf.n if Lf is not None else 0
+        self.version = 0  # bumped by every update_values call
 
     def close(self):
         if getattr(self, "h", None):
@@ -339,6 +340,7 @@ class Preconditioner:
         v = val.to(torch.float64).contiguous()
         self.ctx._check(self.ctx.lib.icpcg_prec_update_values(self.ctx.h, self.h, _ptr(v)))
         self.L = CSR(self.L.row_ptr, self.L.col, v)
+        self.version += 1
 
     def levels(self) -> dict:
         info = self.info()
@@ -395,6 +397,20 @@ class Preconditioner:
         self.ctx._check(self.ctx.lib.icpcg_apply(self.ctx.h, self.h, _ptr(Rc), int(r64), _ptr(Y), _ptr(Z),
                                                  self._width(Rhs)))
         return Y, Z
+
+    def apply_rz(self, Rhs: torch.Tensor):
+        """The preconditioner solve of a PCG step: Y = L^-1 R, Z = L^-T Y for an
+        FP64 block R, and r^T z per column (FP64). Returns (Y, Z, rz)."""
+        self.ctx._bind()
+        if Rhs.dtype != torch.float64:
+            raise ValueError("apply_rz takes a float64 block")
+        Rc = Rhs.contiguous()
+        R = self._width(Rc)
+        Y = torch.empty(Rc.shape, dtype=self.vec_dtype(), device=Rc.device)
+        Z = torch.empty_like(Y)
+        rz = torch.empty(R, dtype=torch.float64, device=Rc.device)
+        self.ctx._check(self.ctx.lib.icpcg_apply_rz(self.ctx.h, self.h, _ptr(Rc), _ptr(Y), _ptr(Z), _ptr(rz), R))
+        return Y, Z, rz
 
     def apply_backward(self, G: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor):
         """Gradients of Z = L^-T L^-1 R given G = dl/dZ. Returns (dR, dL_val)."""
