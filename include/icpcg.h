@@ -257,6 +257,23 @@ icpcg_status icpcg_apply(icpcg_ctx *ctx, const icpcg_prec *P, const void *R, int
 icpcg_status icpcg_apply_rz(icpcg_ctx *ctx, const icpcg_prec *P, const double *R, void *Y, void *Z,
                             double *rz, int64_t nrhs);
 
+/* icpcg_apply_rz for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, kernels and results (bit for bit) as icpcg_apply_rz, but the
+ * reduction partials live in a static device array of the library (65,536
+ * FP64 values, 512 KiB per GPU, held until the process ends) instead of the
+ * context's workspace, and the call makes no allocation of any kind. The
+ * array's address is taken when a context is created (icpcg_create, with its
+ * device current). Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, two contexts, two threads) race and must be
+ * ordered by the caller. Stream-ordered, no synchronization; a dependency
+ * wait that reaches its time limit is reported by the next icpcg_sync on the
+ * context. Errors: ICPCG_E_INVALID (bad arguments, or a device with so many
+ * CUs that nrhs columns of partials would not fit the array), ICPCG_E_DEVICE
+ * (the array's address could not be taken). */
+icpcg_status icpcg_apply_rz_noalloc(icpcg_ctx *ctx, const icpcg_prec *P, const double *R, void *Y, void *Z,
+                                    double *rz, int64_t nrhs);
+
 /* Reverse-mode derivative of Z = L^-T L^-1 R (not in the paper; what training
  * a learned correction of L needs). Given G = dl/dZ and the Y, Z of the
  * forward call: Ybar = L^-1 G, dR = L^-T Ybar, and for every stored (a, b) of

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -39,7 +40,45 @@ const std::string &get_error() { return g_err; }
 
 using namespace icpcg;
 
+// Reduction partials of icpcg_apply_rz_noalloc, for callers that cannot
+// allocate: every call on a device shares that device's copy, which lives
+// until the process ends. Each launch that reads partials first writes all it
+// reads (one value per block and column), so nothing needs clearing between
+// calls. 16 blocks per CU on 256 CUs at 16 columns; the fused backward solve
+// uses at most its resident blocks and the separate r^T z pass at most 1024.
+constexpr int64_t kScratchDoubles = 16 * 256 * 16;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 namespace {
+
+// Device address of `scratch` per device (the host symbol is only a stand-in
+// for it), taken once per device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+int scratch_init(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device id out of range for the no-allocation scratch table");
+    return ICPCG_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_dev[dev]) return ICPCG_OK;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    return ICPCG_E_DEVICE;
+  }
+  g_scratch_dev[dev] = static_cast<double *>(ptr);
+  return ICPCG_OK;
+}
+
+double *scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch_dev[dev];
+}
 
 constexpr int kSmax = kSupernodeMax;
 
@@ -177,6 +216,10 @@ icpcg_status icpcg_create(icpcg_ctx **out, void *stream) {
   if (ensure_flags(ctx) != ICPCG_OK) {
     delete ctx;
     return ICPCG_E_NOMEM;
+  }
+  if (scratch_init(dev) != ICPCG_OK) {
+    delete ctx;
+    return ICPCG_E_DEVICE;
   }
   *out = ctx;
   return ICPCG_OK;
@@ -509,6 +552,40 @@ icpcg_status icpcg_apply_rz(icpcg_ctx *ctx, const icpcg_prec *P, const double *R
   if ((st = fill_pending(Z, P->n * nrhs, lo, s))) return finish(ctx, st);
   if (trsv_fuses_rz(P, Rw, ctx->dev)) {
     RzDot d{R, part, nullptr, nullptr, rz};
+    return finish(ctx, trsv(P, true, Y, !lo, Z, Rw, nrhs, s, ctx->dev, err, nullptr, d));
+  }
+  if ((st = trsv(P, true, Y, !lo, Z, Rw, nrhs, s, ctx->dev, err))) return finish(ctx, st);
+  return finish(ctx, col_dot_out(P->n, Rw, R, Z, lo, part, rz, s));
+}
+
+icpcg_status icpcg_apply_rz_noalloc(icpcg_ctx *ctx, const icpcg_prec *P, const double *R, void *Y, void *Z,
+                                    double *rz, int64_t nrhs) {
+  if (!ctx || !P || !R || !Y || !Z || !rz || !pow2_width(nrhs))
+    return fail(ctx, ICPCG_E_INVALID, "apply_rz_noalloc: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
+  if (not_factor(ctx, P, "apply_rz_noalloc")) return ICPCG_E_INVALID;
+  double *part = scratch_ptr(ctx->dev.id);
+  if (!part) {
+    int st = scratch_init(ctx->dev.id);  // context created on another device than this one
+    if (st) return finish(ctx, st);
+    part = scratch_ptr(ctx->dev.id);
+  }
+  // bound on the blocks either reduction launches (16 per CU, or the separate
+  // pass's 1024), checked before any work is queued
+  const int64_t blocks = std::max<int64_t>(16 * (int64_t)ctx->dev.num_cu, 1024);
+  if (blocks * nrhs > kScratchDoubles)
+    return fail(ctx, ICPCG_E_INVALID,
+                "apply_rz_noalloc: " + std::to_string(nrhs) + " columns on " + std::to_string(ctx->dev.num_cu) +
+                    " CUs need more than the " + std::to_string(kScratchDoubles) + " partials of the static scratch");
+  const bool lo = P->dtype != ICPCG_F64;
+  hipStream_t s = ctx->stream;
+  int *err = &dev_flags(ctx)->err;
+  const int Rw = (int)nrhs;
+  int st;
+  if ((st = fill_pending(Y, P->n * nrhs, lo, s))) return finish(ctx, st);
+  if ((st = trsv(P, false, R, true, Y, Rw, nrhs, s, ctx->dev, err))) return finish(ctx, st);
+  if ((st = fill_pending(Z, P->n * nrhs, lo, s))) return finish(ctx, st);
+  if (trsv_fuses_rz(P, Rw, ctx->dev)) {
+    RzDot d{R, part, nullptr, nullptr, rz, kScratchDoubles};
     return finish(ctx, trsv(P, true, Y, !lo, Z, Rw, nrhs, s, ctx->dev, err, nullptr, d));
   }
   if ((st = trsv(P, true, Y, !lo, Z, Rw, nrhs, s, ctx->dev, err))) return finish(ctx, st);

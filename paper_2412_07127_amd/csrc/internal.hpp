@@ -271,6 +271,9 @@ struct RzDot {
   ColState *cols = nullptr;
   SolveFlags *flags = nullptr;
   double *out = nullptr;
+  // doubles available at `partials` (< 0: sized by the caller for any grid);
+  // a launch whose grid needs more is refused with ICPCG_E_INVALID
+  int64_t partials_cap = -1;
 };
 int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *out, int R,
          int64_t ld, hipStream_t s, const Device &dev, int *err, const int *active = nullptr,

@@ -404,6 +404,11 @@ int launch(const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs
   const int64_t need = (S.nsn + 3) / 4;
   if (need < grid) grid = need;
   if (grid < 1) grid = 1;
+  if (RZ && rz.partials_cap >= 0 && grid * R > rz.partials_cap) {
+    set_error("trsv: the r^T z partials of " + std::to_string(grid) + " blocks x " + std::to_string(R) +
+              " columns exceed the " + std::to_string(rz.partials_cap) + " values of the given buffer");
+    return ICPCG_E_INVALID;
+  }
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kBlock), 0, s, ci, val, S.items.as<SnItem>(), S.nsn, rhs, out,
                      err, dev.wait_ticks, active, rz.r, rz.partials);
   ICPCG_HIP_TRY(hipGetLastError());

@@ -412,6 +412,23 @@ class Preconditioner:
         self.ctx._check(self.ctx.lib.icpcg_apply_rz(self.ctx.h, self.h, _ptr(Rc), _ptr(Y), _ptr(Z), _ptr(rz), R))
         return Y, Z, rz
 
+    def apply_rz_noalloc(self, Rhs: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor, rz: torch.Tensor):
+        """apply_rz into caller-made outputs through the entry point that
+        allocates nothing (its partials live in the library's static device
+        array). Y and Z: the factor's block dtype, R's shape; rz: nrhs FP64."""
+        self.ctx._bind()
+        if Rhs.dtype != torch.float64 or not Rhs.is_contiguous():
+            raise ValueError("apply_rz_noalloc takes a contiguous float64 block")
+        R = self._width(Rhs)
+        for T in (Y, Z):
+            if T.shape != Rhs.shape or T.dtype != self.vec_dtype() or not T.is_contiguous():
+                raise ValueError("Y, Z must be contiguous, R's shape and the factor's block dtype")
+        if rz.dtype != torch.float64 or rz.numel() != R:
+            raise ValueError("rz must hold nrhs float64 values")
+        self.ctx._check(self.ctx.lib.icpcg_apply_rz_noalloc(self.ctx.h, self.h, _ptr(Rhs), _ptr(Y), _ptr(Z),
+                                                            _ptr(rz), R))
+        return Y, Z, rz
+
     def apply_backward(self, G: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor):
         """Gradients of Z = L^-T L^-1 R given G = dl/dZ. Returns (dR, dL_val)."""
         self.ctx._bind()
