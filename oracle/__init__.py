@@ -54,8 +54,18 @@ def _load():
                             C.c_int, P, P, P, P, P]
     lib.orc_apply.argtypes = [i64, P, P, P, P, P, P, P, P, P]
     lib.orc_apply_adjoint.argtypes = [i64, P, P, P, P, P, P, i64, P, P, P, P, P, P, P]
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_max_threads.restype = C.c_int
     _lib = lib
     return lib
+
+
+def set_threads(t: int) -> int:
+    """Threads of the row-parallel loops (SpMV rows, vector updates); returns
+    the count now in effect. Results do not depend on it."""
+    lib = _load()
+    lib.orc_set_threads(int(t))
+    return lib.orc_max_threads()
 
 
 def _p(a):

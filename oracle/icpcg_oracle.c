@@ -22,8 +22,15 @@
  * ascending index order (inner products with compensation, see orc_dot).
  * Build with -ffp-contract=off (no fused multiply-add)
  * and without fast-math so each operation is one IEEE-754 rounding.
+ *
+ * Threads: the product A x and the element-wise vector updates of the PCG
+ * loop split their rows over OpenMP threads (every output element is still
+ * computed by the same sequential code, so results do not depend on the
+ * thread count); inner products, the factorization and the triangular solves
+ * are sequential.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -42,12 +49,20 @@
  * of supplementary Algorithm 1). */
 void orc_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
               const double *x, double *w) {
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     double s = 0.0;
     for (int64_t q = rp[i]; q < rp[i + 1]; ++q) s += v[q] * x[ci[q]];
     w[i] = s;
   }
 }
+
+/* Threads used by the row-parallel loops (<= 0 leaves the OpenMP default). */
+void orc_set_threads(int t) {
+  if (t > 0) omp_set_num_threads(t);
+}
+
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* Inner product sum_i a_i b_i (the r^T z, p^T w and ||r||^2 of supplementary
  * Algorithm 1). The paper fixes no summation order; the products are summed in
@@ -388,6 +403,7 @@ int orc_pcg_run(const orc_prec *P, int64_t n, const int64_t *rp, const int32_t *
     goto done;
   }
   orc_spmv(n, rp, ci, v, x, w);
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) r[i] = b[i] - w[i];
   rr = orc_dot(n, r, r);
   if (hist) hist[0] = sqrt(rr / bb);
@@ -400,13 +416,16 @@ int orc_pcg_run(const orc_prec *P, int64_t n, const int64_t *rp, const int32_t *
       if (!isfinite(rz_new)) { st = ORC_NONFINITE; break; }
       if (!(rz_new > 0.0)) { st = ORC_BREAKDOWN; break; }
       const double beta = k == 0 ? 0.0 : rz_new / rz;
+#pragma omp parallel for schedule(static)
       for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
       orc_spmv(n, rp, ci, v, p, w);
       const double pw = orc_dot(n, p, w);
       if (!isfinite(pw)) { st = ORC_NONFINITE; break; }
       if (!(pw > 0.0)) { st = ORC_BREAKDOWN; break; }
       const double alpha = rz_new / pw;
+#pragma omp parallel for schedule(static)
       for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+#pragma omp parallel for schedule(static)
       for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * w[i];
       rz = rz_new;
       ++k;
@@ -416,6 +435,7 @@ int orc_pcg_run(const orc_prec *P, int64_t n, const int64_t *rp, const int32_t *
     }
     /* true residual */
     orc_spmv(n, rp, ci, v, x, w);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) w[i] = b[i] - w[i];
     trr = orc_dot(n, w, w);
     if (st != ORC_OK || trr <= tol2) break;

@@ -611,3 +611,25 @@ def test_pcg_replacement_below_attainable_accuracy():
         if prev is not None:
             assert res["iters"] > prev
         prev = res["iters"]
+
+
+def test_pcg_bitwise_independent_of_threads():
+    """The row-parallel loops (SpMV rows, vector updates) give the same bits at
+    any thread count: each output element is computed by the same sequential
+    code, and the inner products stay sequential."""
+    p = q1_elasticity(6, 1.0, 5)
+    A = (p.row_ptr, p.col, p.val)
+    st, L, _, _, _ = oracle.ic0_shifted(*A)
+    U = oracle.transpose(*L)
+    b = np.random.default_rng(3).standard_normal(p.n)
+    default = oracle.set_threads(0)
+    try:
+        runs = []
+        for t in (1, 3, 8):
+            assert oracle.set_threads(t) == t
+            runs.append((oracle.pcg(A, L, U, b, rtol=1e-10), oracle.spmv(*A, b)))
+        for r, w in runs[1:]:
+            assert np.array_equal(r["x"], runs[0][0]["x"]) and r["iters"] == runs[0][0]["iters"]
+            assert np.array_equal(w, runs[0][1])
+    finally:
+        oracle.set_threads(default)
