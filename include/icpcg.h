@@ -257,6 +257,18 @@ icpcg_status icpcg_apply(icpcg_ctx *ctx, const icpcg_prec *P, const void *R, int
 icpcg_status icpcg_apply_rz(icpcg_ctx *ctx, const icpcg_prec *P, const double *R, void *Y, void *Z,
                             double *rz, int64_t nrhs);
 
+/* The backward half of icpcg_apply_rz alone, as a PCG step launches it
+ * (supplementary Algorithm 1: the solve with L^T, then r^T z for beta): Z =
+ * L^-T Y and rz[k] = sum_i R_ik Z_ik (FP64). Y and Z are blocks of the
+ * factor's type (FP64, or FP32 for an FP32 / BF16 factor), R is FP64, all
+ * n x nrhs. Like icpcg_trsv it first fills Z with the marker its dependency
+ * waits poll (a PCG step re-arms z in its p update instead). r^T z is fused
+ * into the solve for FP32 / BF16 factors on 2-16 columns (see
+ * ICPCG_FUSE_RZ), else a separate pass forms it. Uses the context's reduction
+ * workspace; stream-ordered. Errors: ICPCG_E_INVALID, ICPCG_E_NOMEM. */
+icpcg_status icpcg_trsv_rz(icpcg_ctx *ctx, const icpcg_prec *P, const void *Y, const double *R, void *Z,
+                           double *rz, int64_t nrhs);
+
 /* icpcg_apply_rz for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * same arguments, kernels and results (bit for bit) as icpcg_apply_rz, but the

@@ -51,7 +51,7 @@ def _load():
     lib.orc_apply_f32.argtypes = [i64, P, P, P, P, P, P, P, P, P, P]
     lib.orc_pcg_simple.argtypes = [i64, P, P, P, C.c_int, P, P, C.c_double, i64, C.c_int, P, P, P, P, P]
     lib.orc_pcg.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, C.c_double, i64, C.c_int,
-                            C.c_int, P, P, P, P, P]
+                            C.c_int, P, P, P, P, P, i64, i64, i64, P, P]
     lib.orc_apply.argtypes = [i64, P, P, P, P, P, P, P, P, P]
     lib.orc_apply_adjoint.argtypes = [i64, P, P, P, P, P, P, i64, P, P, P, P, P, P, P]
     lib.orc_set_threads.argtypes = [C.c_int]
@@ -226,9 +226,12 @@ def apply_f32(L, U, r, prec=1):
     return z
 
 
-def pcg(A, L, U, b, x0=None, rtol=1e-8, max_iter=None, max_replace=3, prec=0, history=False):
+def pcg(A, L, U, b, x0=None, rtol=1e-8, max_iter=None, max_replace=3, prec=0, history=False, snap=None):
     """PCG of supplementary Algorithm 1 (readings in icpcg_oracle.c). Returns a
-    dict: x, status, iters, replacements, relres, true_relres (and hist)."""
+    dict: x, status, iters, replacements, relres, true_relres (and hist).
+    snap = (idx, k_from, k_to): also x[idx] after every step k_from..k_to
+    (inclusive) as "x_snap", a (k_to - k_from + 1, len(idx)) array (rows of
+    steps not reached stay NaN)."""
     rp, ci, v = _csr(*A)
     (lrp, lci, lv), (urp, uci, uv) = _csr(*L), _csr(*U)
     b = np.ascontiguousarray(b, dtype=np.float64)
@@ -241,13 +244,21 @@ def pcg(A, L, U, b, x0=None, rtol=1e-8, max_iter=None, max_replace=3, prec=0, hi
     rr = C.c_double(0)
     tr = C.c_double(0)
     hist = np.zeros(max_iter + 1) if history else None
+    sidx, sfrom, scount, sout = None, 0, 0, None
+    if snap is not None:
+        sidx = np.ascontiguousarray(snap[0], dtype=np.int64)
+        sfrom, scount = int(snap[1]), int(snap[2]) - int(snap[1]) + 1
+        sout = np.full((scount, sidx.shape[0]), np.nan)
     st = _load().orc_pcg(n, _p(rp), _p(ci), _p(v), _p(lrp), _p(lci), _p(lv), _p(urp), _p(uci),
                          _p(uv), _p(b), _p(x), rtol, max_iter, max_replace, prec, C.byref(it),
-                         C.byref(rep), C.byref(rr), C.byref(tr), _p(hist))
+                         C.byref(rep), C.byref(rr), C.byref(tr), _p(hist), sfrom, scount,
+                         0 if sidx is None else sidx.shape[0], _p(sidx), _p(sout))
     out = dict(x=x, status=st, iters=it.value, replacements=rep.value, relres=rr.value,
                true_relres=tr.value)
     if history:
         out["hist"] = hist[:it.value + 1]
+    if snap is not None:
+        out["x_snap"] = sout
     return out
 
 

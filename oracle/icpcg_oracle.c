@@ -384,11 +384,26 @@ static void prec_apply(const orc_prec *P, const double *r, double *z) {
  *  - a converged recurrence whose true residual is still above the tolerance
  *    after max_replace replacements returns ORC_TRUE_RESIDUAL.
  * x holds x_0 on entry and the solution on exit. hist (nullable, max_iter + 1
- * entries) receives ||r_k|| / ||b|| per iteration. */
+ * entries) receives ||r_k|| / ||b|| per iteration. snap (nullable) records
+ * the iterate on a few entries at a range of steps (a copy only; it changes
+ * no arithmetic). */
+typedef struct {
+  int64_t k_from, k_count;  /* steps k_from .. k_from + k_count - 1 */
+  int64_t nidx;
+  const int64_t *idx;       /* entries recorded */
+  double *out;              /* k_count x nidx, row (k - k_from) */
+} orc_snap;
+
+static void snap_take(const orc_snap *sn, int64_t k, const double *x) {
+  if (!sn || k < sn->k_from || k >= sn->k_from + sn->k_count) return;
+  double *row = sn->out + (k - sn->k_from) * sn->nidx;
+  for (int64_t t = 0; t < sn->nidx; ++t) row[t] = x[sn->idx[t]];
+}
+
 int orc_pcg_run(const orc_prec *P, int64_t n, const int64_t *rp, const int32_t *ci,
                 const double *v, const double *b, double *x, double rtol, int64_t max_iter,
                 int max_replace, int64_t *iters_out, int *repl_out, double *relres_out,
-                double *true_relres_out, double *hist) {
+                double *true_relres_out, double *hist, const orc_snap *snap) {
   double *r = (double *)malloc((size_t)n * sizeof(double));
   double *z = (double *)malloc((size_t)n * sizeof(double));
   double *p = (double *)calloc((size_t)n, sizeof(double));
@@ -429,6 +444,7 @@ int orc_pcg_run(const orc_prec *P, int64_t n, const int64_t *rp, const int32_t *
       for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * w[i];
       rz = rz_new;
       ++k;
+      snap_take(snap, k, x);
       rr = orc_dot(n, r, r);
       if (hist) hist[k] = sqrt(rr / bb);
       if (!isfinite(rr)) { st = ORC_NONFINITE; break; }
@@ -461,7 +477,10 @@ int orc_pcg(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
             const int64_t *urp, const int32_t *uci, const double *uv,
             const double *b, double *x, double rtol, int64_t max_iter, int max_replace,
             int prec, int64_t *iters_out, int *repl_out, double *relres_out,
-            double *true_relres_out, double *hist) {
+            double *true_relres_out, double *hist, int64_t snap_from, int64_t snap_count,
+            int64_t snap_nidx, const int64_t *snap_idx, double *snap_out) {
+  orc_snap sn = {snap_from, snap_count, snap_nidx, snap_idx, snap_out};
+  const orc_snap *snap = (snap_out && snap_count > 0 && snap_nidx > 0) ? &sn : NULL;
   orc_prec P;
   memset(&P, 0, sizeof(P));
   P.n = n; P.lrp = lrp; P.lci = lci; P.lv = lv; P.urp = urp; P.uci = uci; P.uv = uv;
@@ -478,7 +497,7 @@ int orc_pcg(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
     P.y = (double *)malloc((size_t)n * sizeof(double));
   }
   int st = orc_pcg_run(&P, n, rp, ci, v, b, x, rtol, max_iter, max_replace, iters_out,
-                       repl_out, relres_out, true_relres_out, hist);
+                       repl_out, relres_out, true_relres_out, hist, snap);
   free(l32); free(u32); free(P.y32); free(P.z32); free(P.y);
   return st;
 }
@@ -550,7 +569,7 @@ int orc_pcg_simple(int64_t n, const int64_t *rp, const int32_t *ci, const double
     P.diag = d;
   }
   int st = orc_pcg_run(&P, n, rp, ci, v, b, x, rtol, max_iter, max_replace, iters_out,
-                       repl_out, relres_out, true_relres_out, hist);
+                       repl_out, relres_out, true_relres_out, hist, NULL);
   free(d);
   return st;
 }

@@ -92,6 +92,7 @@ def load():
         "icpcg_apply": ([P, P, P, st, P, P, i64], st),
         "icpcg_apply_rz": ([P, P, P, P, P, P, i64], st),
         "icpcg_apply_rz_noalloc": ([P, P, P, P, P, P, i64], st),
+        "icpcg_trsv_rz": ([P, P, P, P, P, P, i64], st),
         "icpcg_apply_backward": ([P, P, P, P, P, P, P, P, i64], st),
         "icpcg_solve": ([P, C.POINTER(Csr), P, P, P, i64, C.POINTER(SolveOpts), C.POINTER(ColInfo)], st),
         "icpcg_sync": ([P], st),

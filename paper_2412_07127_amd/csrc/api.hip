@@ -558,6 +558,28 @@ icpcg_status icpcg_apply_rz(icpcg_ctx *ctx, const icpcg_prec *P, const double *R
   return finish(ctx, col_dot_out(P->n, Rw, R, Z, lo, part, rz, s));
 }
 
+icpcg_status icpcg_trsv_rz(icpcg_ctx *ctx, const icpcg_prec *P, const void *Y, const double *R, void *Z, double *rz,
+                           int64_t nrhs) {
+  if (!ctx || !P || !Y || !R || !Z || !rz || !pow2_width(nrhs))
+    return fail(ctx, ICPCG_E_INVALID, "trsv_rz: bad arguments (nrhs must be 1, 2, 4, 8 or 16)");
+  if (not_factor(ctx, P, "trsv_rz")) return ICPCG_E_INVALID;
+  const bool lo = P->dtype != ICPCG_F64;
+  hipStream_t s = ctx->stream;
+  Workspace &ws = ctx->ws;
+  if (ws.partials.reserve((size_t)kMaxDotBlocks * nrhs * 2 * 8)) return finish(ctx, ICPCG_E_NOMEM);
+  double *part = ws.partials.as<double>();
+  int *err = &dev_flags(ctx)->err;
+  const int Rw = (int)nrhs;
+  int st;
+  if ((st = fill_pending(Z, P->n * nrhs, lo, s))) return finish(ctx, st);
+  if (trsv_fuses_rz(P, Rw, ctx->dev)) {
+    RzDot d{R, part, nullptr, nullptr, rz};
+    return finish(ctx, trsv(P, true, Y, !lo, Z, Rw, nrhs, s, ctx->dev, err, nullptr, d));
+  }
+  if ((st = trsv(P, true, Y, !lo, Z, Rw, nrhs, s, ctx->dev, err))) return finish(ctx, st);
+  return finish(ctx, col_dot_out(P->n, Rw, R, Z, lo, part, rz, s));
+}
+
 icpcg_status icpcg_apply_rz_noalloc(icpcg_ctx *ctx, const icpcg_prec *P, const double *R, void *Y, void *Z,
                                     double *rz, int64_t nrhs) {
   if (!ctx || !P || !R || !Y || !Z || !rz || !pow2_width(nrhs))

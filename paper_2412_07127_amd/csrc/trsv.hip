@@ -32,6 +32,8 @@
 //    Partial sums meet in a fixed butterfly (deterministic).
 //  * Factor values may be FP64, FP32 or bfloat16 (widened to FP32); FP32 and
 //    bfloat16 factors run FP32 arithmetic.
+#include <utility>
+
 #include "reduce.hpp"
 
 namespace icpcg {
@@ -46,6 +48,29 @@ __device__ __forceinline__ T xor_sum_hi(T v) {
 #pragma unroll
   for (int b = 32; b >= (1 << LO); b >>= 1) v += __shfl_xor(v, b, ICPCG_WAVE);
   return v;
+}
+
+// Lane K of each 16-lane row of the wave, to every lane of that row (DPP
+// row_newbcast). Source lanes are in the reader's own row, so a row that is
+// active as a whole reads defined values.
+template <int K>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x150 + K, 0xf, 0xf, true));
+}
+template <int K>
+__device__ __forceinline__ int row_bcast(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xf, 0xf, true);
+}
+
+// f(integral_constant<int, K>) for K = 0 .. N-1 in order (DPP controls must be
+// compile-time constants).
+template <typename F, int... K>
+__device__ __forceinline__ void static_for_impl(F &f, std::integer_sequence<int, K...>) {
+  (f(std::integral_constant<int, K>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 // Row start of row a+u of a supernode from the first row's start: lower rows
@@ -110,8 +135,20 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
   constexpr int SLOTS = 64 / LPR;                // entry slots per wave
   constexpr int NDB = kSmax * (kSmax + 1) / 2;  // stored entries of a dense diagonal block
   constexpr unsigned long long kRowMask = LPR >= 64 ? ~0ull : ((1ull << LPR) - 1);
+  // Window by broadcast (16 columns of 4-byte values: a slot's lanes form one
+  // 16-lane DPP row): each lane loads one window entry (its column index and
+  // its values in the supernode's rows) and the row's lanes take entry k from
+  // lane k by row broadcast, instead of every lane loading and holding all QD
+  // entries (about 30 fewer registers per lane, one more resident wave per SIMD).
+  constexpr bool kBC = LPR == 16 && CPL == 1 && sizeof(TA) == 4 && QD <= 16;
+  constexpr bool kBCJ = false;  // column indices by broadcast
+  constexpr bool kBCV = kBC;    // factor values by broadcast
   const int lane = threadIdx.x & 63, slot = lane / LPR, c0 = (lane % LPR) * CPL;
-  const int64_t w0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  // wave index and wave count as wave-uniform values: the item records then
+  // come through the scalar unit, whose count (lgkmcnt) a wave waits on at the
+  // top of each item instead of the vector count, which on this architecture
+  // also holds the acknowledgements of the previous item's published rows
+  const int64_t w0 = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6));
   const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
   double dot[CPL];
 #pragma unroll
@@ -144,21 +181,41 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
     // done before the wait, which keeps the path after it shortest
     // (measured: 2-7% faster at one column, 11% slower at sixteen).
     constexpr bool kRaw = R > 1;
-    int jj[QD];
-    TV vv[QD][kSmax];  // raw (R > 1)
-    TA vw[QD][kSmax];  // widened (R == 1)
+    int jj[kBCJ ? 1 : QD];
+    TV vv[kBCV ? 1 : QD][kSmax];  // raw (R > 1)
+    TA vw[kBCV ? 1 : QD][kSmax];  // widened (R == 1)
+    // broadcast forms: lane (slot, c) holds the slot's window entry c
+    // (q = slot + c * SLOTS)
+    int jown = 0;
+    TV vown[kSmax];
+    {
+      const int qo = slot + c0 * SLOTS;
+      const int qoc = qo < m ? qo : m - 1;
+      if constexpr (kBCJ) jown = ci[pcol + (qoc > 0 ? qoc : 0)];
+      if constexpr (kBCV) {
+#pragma unroll
+        for (int u = 0; u < kSmax; ++u) {
+          const int uc = u < sz ? u : sz - 1;
+          vown[u] = val[m > 0 ? (UPPER ? ro[uc] + (sz - uc) + qoc : ro[uc] + qoc) : ro[uc]];
+        }
+      }
+    }
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
       const int q = slot + k * SLOTS;
       const int qc = q < m ? q : m - 1;
-      jj[k] = q < m ? ci[pcol + q] : 0;
+      // several columns: from a clamped in-row place, no branch (the gather of
+      // a place past the row is skipped)
+      if constexpr (!kBCJ) jj[k] = kRaw ? ci[pcol + (qc > 0 ? qc : 0)] : (q < m ? ci[pcol + q] : 0);
+      if constexpr (!kBCV) {
 #pragma unroll
-      for (int u = 0; u < kSmax; ++u) {
-        if constexpr (kRaw) {
-          const int uc = u < sz ? u : sz - 1;
-          vv[k][u] = val[m > 0 ? (UPPER ? ro[uc] + (sz - uc) + qc : ro[uc] + qc) : ro[uc]];
-        } else {
-          vw[k][u] = (q < m && u < sz) ? widen<TA>(val[UPPER ? ro[u] + (sz - u) + q : ro[u] + q]) : TA(0);
+        for (int u = 0; u < kSmax; ++u) {
+          if constexpr (kRaw) {
+            const int uc = u < sz ? u : sz - 1;
+            vv[k][u] = val[m > 0 ? (UPPER ? ro[uc] + (sz - uc) + qc : ro[uc] + qc) : ro[uc]];
+          } else {
+            vw[k][u] = (q < m && u < sz) ? widen<TA>(val[UPPER ? ro[u] + (sz - u) + q : ro[u] + q]) : TA(0);
+          }
         }
       }
     }
@@ -224,16 +281,18 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
     // pending the lanes covering one pending row poll it together (one
     // contiguous row per load) and the pending ones are loaded again
     U xb[QD][CPL];
-#pragma unroll
-    for (int k = 0; k < QD; ++k) {
-      const int q = slot + k * SLOTS;
-      if (q < m) {
-        load_elems<TA, CPL>(out + (int64_t)jj[k] * R + c0, xb[k]);
+    static_for<QD>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      int jk;
+      if constexpr (kBCJ) jk = row_bcast<k>(jown);
+      else jk = jj[k];
+      if (slot + k * SLOTS < m) {
+        load_elems<TA, CPL>(out + (int64_t)jk * R + c0, xb[k]);
       } else {
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) xb[k][cc] = 0;
       }
-    }
+    });
     for (;;) {
       bool pend = false;
       int pk = 0;
@@ -245,11 +304,15 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
       const int leader = 63 - __clzll(mask);  // the nearest rows sit last
       const int pslot = __shfl(slot, leader, ICPCG_WAVE);
       const int pkk = __shfl(pk, leader, ICPCG_WAVE);
-      if (slot == pslot) {
-        int jp = 0;
+      int jp = 0;
+      if constexpr (kBCJ) {
+        jp = __shfl(jown, pslot * LPR + pkk, ICPCG_WAVE);  // every lane active here
+      } else {
 #pragma unroll
         for (int k = 0; k < QD; ++k)
           if (k == pkk) jp = jj[k];
+      }
+      if (slot == pslot) {
         const TA *p = out + (int64_t)jp * R + c0;
         U v[CPL];
         load_elems<TA, CPL>(p, v);
@@ -273,24 +336,42 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
             for (int cc = 0; cc < CPL; ++cc) xb[k][cc] = v[cc];
           }
       }
-#pragma unroll
-      for (int k = 0; k < QD; ++k)
-        if (any_pending<TA, CPL>(xb[k])) load_elems<TA, CPL>(out + (int64_t)jj[k] * R + c0, xb[k]);
+      static_for<QD>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        int jk;
+        if constexpr (kBCJ) jk = row_bcast<k>(jown);
+        else jk = jj[k];
+        if (any_pending<TA, CPL>(xb[k])) load_elems<TA, CPL>(out + (int64_t)jk * R + c0, xb[k]);
+      });
     }
     TA acc[kSmax][CPL];
 #pragma unroll
     for (int u = 0; u < kSmax; ++u)
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) acc[u][cc] = TA(0);
+    if constexpr (kBCV) {
+      // entries past the row gathered x = 0 and their (clamped) factor values
+      // are finite, so their products are exactly 0: no branch
+      TA vwn[kSmax];
 #pragma unroll
-    for (int k = 0; k < QD; ++k) {
-      const int q = slot + k * SLOTS;
-      if (q < m) {
+      for (int u = 0; u < kSmax; ++u) vwn[u] = widen<TA>(vown[u]);
+      static_for<QD>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const TA x = bitcast<TA>(xb[k][0]);
 #pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) {
-          const TA x = bitcast<TA>(xb[k][cc]);
+        for (int u = 0; u < kSmax; ++u) acc[u][0] += row_bcast<k>(vwn[u]) * x;
+      });
+    } else {
 #pragma unroll
-          for (int u = 0; u < kSmax; ++u) acc[u][cc] += fval(k, u) * x;
+      for (int k = 0; k < QD; ++k) {
+        const int q = slot + k * SLOTS;
+        if (q < m) {
+#pragma unroll
+          for (int cc = 0; cc < CPL; ++cc) {
+            const TA x = bitcast<TA>(xb[k][cc]);
+#pragma unroll
+            for (int u = 0; u < kSmax; ++u) acc[u][cc] += fval(k, u) * x;
+          }
         }
       }
     }

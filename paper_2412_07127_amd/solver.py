@@ -412,6 +412,21 @@ class Preconditioner:
         self.ctx._check(self.ctx.lib.icpcg_apply_rz(self.ctx.h, self.h, _ptr(Rc), _ptr(Y), _ptr(Z), _ptr(rz), R))
         return Y, Z, rz
 
+    def trsv_rz(self, Y: torch.Tensor, Rhs: torch.Tensor, Z: torch.Tensor = None, rz: torch.Tensor = None):
+        """Backward solve Z = L^-T Y with r^T z per column, as a PCG step
+        launches it (fused for FP32 / BF16 factors on 2-16 columns). Y: the
+        factor's block dtype; R: FP64 of Y's shape. Returns (Z, rz)."""
+        self.ctx._bind()
+        if Rhs.dtype != torch.float64 or not Rhs.is_contiguous():
+            raise ValueError("trsv_rz takes a contiguous float64 R")
+        if Y.shape != Rhs.shape or Y.dtype != self.vec_dtype() or not Y.is_contiguous():
+            raise ValueError("Y must be contiguous, R's shape and the factor's block dtype")
+        R = self._width(Rhs)
+        Z = torch.empty_like(Y) if Z is None else Z
+        rz = torch.empty(R, dtype=torch.float64, device=Y.device) if rz is None else rz
+        self.ctx._check(self.ctx.lib.icpcg_trsv_rz(self.ctx.h, self.h, _ptr(Y), _ptr(Rhs), _ptr(Z), _ptr(rz), R))
+        return Z, rz
+
     def apply_rz_noalloc(self, Rhs: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor, rz: torch.Tensor):
         """apply_rz into caller-made outputs through the entry point that
         allocates nothing (its partials live in the library's static device

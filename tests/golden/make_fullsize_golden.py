@@ -1,18 +1,20 @@
-"""Writes tests/golden/q1_100_oracle.json: FP64 oracle solves of the 100^3
-elasticity workload (3,060,300 DOF, sigma 2.0, seed 1003), for the full-size
-GPU parity tests and the benchmark's error-against-oracle figure.
+"""Writes tests/golden/q1_100_oracle.json and q1_100_oracle_x.npz: FP64 oracle
+solves of the 100^3 elasticity workload (3,060,300 DOF, sigma 2.0, seed 1003),
+for the full-size GPU parity tests and the benchmark's error-against-oracle
+figure.
 
-Calls only the oracle and the input generator. Content, per right-hand side
-(the body load + noise of seed 2003, and load cases 0 and 1 of the sixteen
-traction columns of seed 2004):
-  * the converged solve (rtol 1e-8, true residual checked): status, k0,
+Calls only the oracle and the input generator. Per right-hand side (the body
+load + noise of seed 2003, and load cases 0 and 1 of the sixteen traction
+columns of seed 2004):
+  * JSON: the converged solve (rtol 1e-8, true residual checked): status, k0,
     relative and true residual, the recurrence residual of every step;
-  * x sampled every 997th entry at k0 - 1, k0 and k0 + 1 steps (the last two
-    of runs with rtol 0 and max_iter fixed), so that a GPU solve stopping
-    within one step of the oracle is compared with the oracle at its own
-    step count.
+  * NPZ: x sampled every 997th entry after every step k0 - W .. k0 + W
+    (W = 8; one run with rtol 0 that goes past k0 records them), so a GPU
+    solve that stops near k0 is compared with the oracle at its own step
+    count.
 The factor (IC(0) with the global shift rule) is computed once; the solves run
-in forked worker processes that share it. Takes about ten minutes on 8 cores.
+in forked worker processes that share it, one thread each. Takes about 15
+minutes on 8 cores.
 """
 
 import json
@@ -30,21 +32,26 @@ import oracle  # noqa: E402
 from synth import WORKLOADS, build_workload, traction_loads  # noqa: E402
 
 OUT = os.path.join(HERE, "q1_100_oracle.json")
+OUT_X = os.path.join(HERE, "q1_100_oracle_x.npz")
 STRIDE = 997
 TRACTION_COLUMNS = (0, 1)
+W = 8
+# the recording run goes to K_HI steps and keeps K_LO .. K_HI; every k0 +- W must
+# fall inside (asserted)
+K_LO, K_HI = 760, 850
 
 _S = {}  # matrix, factor and right-hand sides, inherited by the forked workers
 
 
 def _solve(job):
-    name, k = job
+    name, record = job
+    oracle.set_threads(1)
     A, L, U = _S["A"], _S["L"], _S["U"]
     b = _S["rhs"][name]
-    if k is None:
-        r = oracle.pcg(A, L, U, b, rtol=1e-8, history=True)
-    else:
-        r = oracle.pcg(A, L, U, b, rtol=0.0, max_iter=k, max_replace=0)
-    return name, k, r
+    if not record:
+        return name, record, oracle.pcg(A, L, U, b, rtol=1e-8, history=True)
+    return name, record, oracle.pcg(A, L, U, b, rtol=0.0, max_iter=K_HI, max_replace=0,
+                                    snap=(_S["idx"], K_LO, K_HI))
 
 
 def main():
@@ -59,37 +66,38 @@ def main():
     rhs = {"body": b}
     for c in TRACTION_COLUMNS:
         rhs[f"traction{c}"] = np.ascontiguousarray(B[:, c])
-    _S.update(A=A, L=L, U=U, rhs=rhs)
     idx = np.arange(0, prob.n, STRIDE)
-    ctx = mp.get_context("fork")
-    with ctx.Pool(len(rhs)) as pool:
-        conv = {name: r for name, _, r in pool.map(_solve, [(name, None) for name in rhs])}
-    jobs = []
+    _S.update(A=A, L=L, U=U, rhs=rhs, idx=idx)
+    jobs = [(name, rec) for name in rhs for rec in (False, True)]
+    with mp.get_context("fork").Pool(len(jobs)) as pool:
+        res = pool.map(_solve, jobs)
+    conv = {name: r for name, rec, r in res if not rec}
+    recd = {name: r for name, rec, r in res if rec}
+    cases, xw = {}, {}
     for name, r in conv.items():
         assert r["status"] == oracle.OK and r["replacements"] == 0, (name, r["status"])
-        jobs += [(name, r["iters"] - 1), (name, r["iters"] + 1)]
-    with ctx.Pool(min(8, len(jobs))) as pool:
-        near = pool.map(_solve, jobs)
-    cases = {}
-    for name, r in conv.items():
         k0 = r["iters"]
-        xs = {str(k0): r["x"][idx].tolist()}
-        for nm, k, rk in near:
-            if nm == name:
-                assert rk["iters"] == k and rk["status"] == oracle.MAXITER
-                xs[str(k)] = rk["x"][idx].tolist()
+        assert K_LO <= k0 - W and k0 + W <= K_HI, (name, k0)
+        snap = recd[name]["x_snap"]
+        win = snap[k0 - W - K_LO:k0 + W - K_LO + 1]
+        assert np.isfinite(win).all()
+        # the recording run is the same iteration: it passes k0 with the same iterate
+        assert np.array_equal(win[W], r["x"][idx])
+        xw[name] = win
         cases[name] = dict(
             status=r["status"], iters=k0, replacements=r["replacements"], relres=r["relres"],
             true_relres=r["true_relres"], x_norm=float(np.linalg.norm(r["x"])),
-            relres_history=r["hist"].tolist(), x_sample_at=xs)
+            relres_history=r["hist"].tolist(), x_window_steps=[k0 - W, k0 + W])
     out = dict(
         what="FP64 oracle on the 100^3 Q1 elasticity workload (sigma 2.0, seed 1003): IC(0) with the global "
-             "shift rule, then PCG to rtol 1e-8 (true residual checked) from x0 = 0; x sampled every "
-             f"{STRIDE}th entry at the converged step count k0 and at k0 - 1, k0 + 1 (runs with rtol 0)",
+             "shift rule, then PCG to rtol 1e-8 (true residual checked) from x0 = 0; the iterates on every "
+             f"{STRIDE}th entry after steps k0 - {W} .. k0 + {W} are in q1_100_oracle_x.npz (key = case name, "
+             "row = step - (k0 - W))",
         rhs={"body": "body load (0,0,-1) + N(0, 0.1^2) noise, seed 2003",
              **{f"traction{c}": f"load case {c} of traction_loads(100, 16, {seed_t})" for c in TRACTION_COLUMNS}},
         n=prob.n, nnz=prob.nnz, alpha=alpha, restarts=restarts, min_pivot=minpiv,
-        sample_stride=STRIDE, sample_index=idx.tolist(), cases=cases, seconds=time.time() - t0)
+        sample_stride=STRIDE, sample_index=idx.tolist(), window=W, cases=cases, seconds=time.time() - t0)
+    np.savez(OUT_X, **xw)
     with open(OUT, "w") as f:
         json.dump(out, f)
     print(json.dumps({k: (v["iters"], v["true_relres"]) for k, v in cases.items()}), f"{time.time() - t0:.0f} s")

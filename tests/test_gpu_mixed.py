@@ -104,6 +104,20 @@ def test_apply_rz_matches_oracle(ctx, ctx_unfused, dt, R, fused):
         assert abs(rzh[k] - oracle.dot(Rh[:, k], z)) <= tol * abs(rzh[k])
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("R", [1, 4, 16])
+def test_trsv_rz_is_apply_rz_backward_half(ctx, dt, R):
+    """The backward solve with r^T z alone (the launch a PCG step makes) gives
+    the Z and r^T z of apply_rz bit for bit when fed apply_rz's Y."""
+    _, L, U, _ = oracle_factor("w:q1_40")
+    n = L[0].shape[0] - 1
+    P = ctx.prec(to_gpu(L), dt)
+    Rt = torch.from_numpy(np.random.default_rng(40 + R).standard_normal((n, R) if R > 1 else n)).cuda()
+    Y, Z, rz = P.apply_rz(Rt)
+    Z2, rz2 = P.trsv_rz(Y, Rt)
+    assert torch.equal(Z, Z2) and torch.equal(rz, rz2)
+
+
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
 def test_apply_rz_fused_equals_unfused(ctx, ctx_unfused, dt):
     """The fused form changes only where r^T z is summed: Z is bit-identical."""

@@ -633,3 +633,19 @@ def test_pcg_bitwise_independent_of_threads():
             assert np.array_equal(w, runs[0][1])
     finally:
         oracle.set_threads(default)
+
+
+def test_pcg_snapshots_are_the_iterates():
+    """The recorded entries at step k equal x after a run stopped at k."""
+    p = q1_elasticity(5, 1.0, 9)
+    A = (p.row_ptr, p.col, p.val)
+    st, L, _, _, _ = oracle.ic0_shifted(*A)
+    U = oracle.transpose(*L)
+    b = np.random.default_rng(1).standard_normal(p.n)
+    idx = np.arange(0, p.n, 7)
+    r = oracle.pcg(A, L, U, b, rtol=1e-10, snap=(idx, 3, 9))
+    for k in range(3, 10):
+        rk = oracle.pcg(A, L, U, b, rtol=0.0, max_iter=k, max_replace=0)
+        assert np.array_equal(r["x_snap"][k - 3], rk["x"][idx])
+    late = oracle.pcg(A, L, U, b, rtol=1e-10, snap=(idx, r["iters"], r["iters"] + 2))
+    assert np.array_equal(late["x_snap"][0], r["x"][idx]) and np.isnan(late["x_snap"][1:]).all()
