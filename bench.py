@@ -374,6 +374,7 @@ def main():
         return ctx.permute_rows(pm, Xp, inverse=True), info
 
     def run_single(order, Mx, Px, name):
+        log(f"{name}: one solve ...")
         torch.cuda.synchronize()
         t = time.perf_counter()
         X, info = solve_in(order, Mx, Px, bt)
@@ -402,6 +403,7 @@ def main():
     tunes = {}
 
     def multi(order, Mx, Px, name, steps, warmup):
+        log(f"{name}: autotune, {warmup} warm-up and {steps} timed steps ...")
         tunes[name] = ctx.autotune(Mx, Px, args.nrhs)  # the width choice is setup, outside the timing
         for _ in range(warmup):
             solve_in(order, Mx, Px, Bt, graph=True)
@@ -429,9 +431,6 @@ def main():
     if not args.skip_single:
         multi("colour", Mc, Pc32, "multi16_fp32_L_multicolour", 1, 0)
         multi("block", Mb, Pb32, "multi16_fp32_L_block_multicolour", 1, 1)
-    # the same 16 load cases with the factor applied in FP64 (separates the
-    # batching gain from the precision gain)
-    multi("natural", M, P64, "multi16_fp64_L", 1, 1)
     # headline: natural order, 16 load cases, FP32 factor, FP64 recurrences
     total, step_s = multi("natural", M, P32, "multi16_fp32_L", args.steps, args.warmup)
     value = args.nrhs * args.steps / total
@@ -443,6 +442,7 @@ def main():
     R = args.nrhs if args.nrhs in (1, 2, 4, 8, 16) else 16
     # the block multicolour order's kernels first, the headline's last (their
     # dispatches are then the last ones of a profiled run)
+    log(f"per-kernel timing at width {R} ...")
     kt_b = time_kernels(ctx, Mb, Pb32, R, args.kernel_reps, torch) if not args.skip_single else None
     kt = time_kernels(ctx, M, P32, R, args.kernel_reps, torch)
     n, nnzA, nnzL = prob.n, prob.nnz, pinfo["nnz"]
@@ -476,6 +476,7 @@ def main():
     # loss + gradient pass (a training step's work) over nnz(L) edges
     gnn = None
     if not args.skip_single:
+        log("learned correction at this size: one forward, one loss + gradient ...")
         from paper_2412_07127_amd import gnn as G
         g = G.GNNGraph(ctx, A, P64)
         theta = G.init_params(0, zero_output=False)

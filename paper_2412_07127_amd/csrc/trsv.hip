@@ -144,11 +144,12 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
   constexpr bool kBCJ = false;  // column indices by broadcast
   constexpr bool kBCV = kBC;    // factor values by broadcast
   const int lane = threadIdx.x & 63, slot = lane / LPR, c0 = (lane % LPR) * CPL;
-  // wave index and wave count as wave-uniform values: the item records then
+  // kBC kernels: the wave index as a wave-uniform value, so the item records
   // come through the scalar unit, whose count (lgkmcnt) a wave waits on at the
   // top of each item instead of the vector count, which on this architecture
   // also holds the acknowledgements of the previous item's published rows
-  const int64_t w0 = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6));
+  const int64_t wl = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int64_t w0 = kBC ? (int64_t)__builtin_amdgcn_readfirstlane((int)wl) : wl;
   const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
   double dot[CPL];
 #pragma unroll
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
     {
       const int qo = slot + c0 * SLOTS;
       const int qoc = qo < m ? qo : m - 1;
-      if constexpr (kBCJ) jown = ci[pcol + (qoc > 0 ? qoc : 0)];
+      if constexpr (kBCJ) jown = ci[m > 0 ? pcol + qoc : ro[0]];
       if constexpr (kBCV) {
 #pragma unroll
         for (int u = 0; u < kSmax; ++u) {
@@ -204,9 +205,10 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
     for (int k = 0; k < QD; ++k) {
       const int q = slot + k * SLOTS;
       const int qc = q < m ? q : m - 1;
-      // several columns: from a clamped in-row place, no branch (the gather of
-      // a place past the row is skipped)
-      if constexpr (!kBCJ) jj[k] = kRaw ? ci[pcol + (qc > 0 ? qc : 0)] : (q < m ? ci[pcol + q] : 0);
+      // kBC kernels: from a clamped in-row place, no branch (the gather of a
+      // place past the row is skipped; a supernode with no off-block entry
+      // reads its own first entry)
+      if constexpr (!kBCJ) jj[k] = kBC ? ci[m > 0 ? pcol + qc : ro[0]] : (q < m ? ci[pcol + q] : 0);
       if constexpr (!kBCV) {
 #pragma unroll
         for (int u = 0; u < kSmax; ++u) {
