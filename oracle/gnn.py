@@ -231,11 +231,10 @@ def loss(g: Graph, Lval, z):
     return float(r @ r / (az @ az))
 
 
-def loss_and_grad(g: Graph, theta, z, x=None):
-    """(loss, d loss / d theta) with the backward pass written out."""
-    P = unpack(theta)
-    out, C = forward(g, theta, x, keep=True)
-    Lval = corrected_factor(g, out, C["s"])
+def loss_and_grad_L(g: Graph, Lval, z):
+    """Eq. 5's loss for probe z and its derivative with respect to L's stored
+    values: with u = L^T z and r = L L^T z - A z, d||r||^2 / dL_ab =
+    2 (r_a u_b + z_a (L^T r)_b), divided by ||A z||^2."""
     arp, aci, aval = g.A
     az = coo_matvec(g.a_rows, aci, aval, z)
     u = np.bincount(g.c, weights=Lval * z[g.r], minlength=g.n)      # L^T z
@@ -245,6 +244,15 @@ def loss_and_grad(g: Graph, theta, z, x=None):
     lval = float(r @ r / den)
     ltr = np.bincount(g.c, weights=Lval * r[g.r], minlength=g.n)    # L^T r
     dL = 2.0 / den * (r[g.r] * u[g.c] + z[g.r] * ltr[g.c])
+    return lval, dL
+
+
+def loss_and_grad(g: Graph, theta, z, x=None):
+    """(loss, d loss / d theta) with the backward pass written out."""
+    P = unpack(theta)
+    out, C = forward(g, theta, x, keep=True)
+    Lval = corrected_factor(g, out, C["s"])
+    lval, dL = loss_and_grad_L(g, Lval, z)
     dout = np.where(g.diag, dL * Lval / 2.0, dL * np.sqrt(C["s"]))
 
     G = {name: np.zeros(shape) for name, shape in param_layout()}

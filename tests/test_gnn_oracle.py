@@ -244,3 +244,96 @@ def test_corrected_factor_constant_output_diagonal():
     assert np.allclose((Lp[dg] / g.Lic[dg]) ** 2, np.exp(c), rtol=1e-14, atol=0)
     off = Lp[~dg] - g.Lic[~dg]
     assert np.allclose(off, off[0], rtol=1e-12, atol=0) and off[0] > 0
+
+
+def test_loss_gradient_in_L_matches_central_differences():
+    """d(Eq. 5 loss)/dL on every stored entry of L, against central differences
+    of the loss itself (a slip in either product of the closed form, or a
+    transposed operand, fails)."""
+    A, L, g = small_graph(E=2, sigma=1.5, seed=21)
+    rng = np.random.default_rng(3)
+    Lval = g.Lic * (1.0 + 0.1 * rng.standard_normal(g.Lic.size))
+    z = rng.choice([-1.0, 1.0], g.n)
+    f, dL = G.loss_and_grad_L(g, Lval, z)
+    assert f == pytest.approx(G.loss(g, Lval, z), rel=1e-14)
+    h = 1e-6
+    for q in range(Lval.size):
+        lp = Lval.copy(); lp[q] += h
+        lm = Lval.copy(); lm[q] -= h
+        fd = (G.loss(g, lp, z) - G.loss(g, lm, z)) / (2 * h)
+        assert abs(fd - dL[q]) <= 1e-6 * abs(dL[q]) + 1e-8 * np.abs(dL).max(), q
+
+
+def _iters(A, Lval, L, b):
+    Lx = (L[0], L[1], Lval)
+    return oracle.pcg(A, Lx, oracle.transpose(*Lx), b, rtol=1e-8)["iters"]
+
+
+def _adam_on_values(Lval0, grad_fn, steps, lr, keep_diag_positive):
+    th = Lval0.copy()
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for t in range(1, steps + 1):
+        gsum = grad_fn(th, t)
+        th, m, v = G.adam_step(th, gsum, m, v, t, lr)
+        th = np.where(keep_diag_positive, np.maximum(th, 1e-3 * np.abs(Lval0)), th)
+    return th
+
+
+def test_ceiling_free_factor_under_eq5():
+    """How far Eq. (5) can take L at all, with no network: Adam on L's stored
+    values themselves (the largest correction any network on this pattern
+    could output), from L_IC, with fresh probes every step. The Eq. (5) loss
+    falls by about a third, while PCG needs no fewer iterations than with
+    L_IC: on these elasticity matrices Eq. (5)'s optimum on tril(A)'s pattern
+    is not a better preconditioner than IC(0). (An experiment recorded as a
+    test: its numbers are printed.)"""
+    A, L, g = small_graph(E=4, sigma=1.5, seed=31)
+    b = np.random.default_rng(4).standard_normal(g.n)
+    rng = np.random.default_rng(5)
+    zs_eval = [rng.choice([-1.0, 1.0], g.n) for _ in range(16)]
+    mean_loss = lambda Lv: np.mean([G.loss(g, Lv, z) for z in zs_eval])
+
+    def grad(th, t):
+        zs = [rng.choice([-1.0, 1.0], g.n) for _ in range(8)]
+        return sum(G.loss_and_grad_L(g, th, z)[1] for z in zs) / len(zs)
+
+    Lopt = _adam_on_values(g.Lic, grad, steps=300, lr=2e-3 * np.abs(g.Lic).mean(), keep_diag_positive=g.diag)
+    l0, l1 = mean_loss(g.Lic), mean_loss(Lopt)
+    k0, k1 = _iters(A, g.Lic, L, b), _iters(A, Lopt, L, b)
+    print(f"Eq. 5 loss {l0:.4e} -> {l1:.4e} ({100 * (l1 - l0) / l0:+.1f}%); PCG iterations {k0} -> {k1}")
+    assert l1 < 0.85 * l0
+    assert k1 >= k0 - 1
+
+
+def test_ceiling_free_factor_under_solve_loss():
+    """The same with the loss the preconditioner is used for:
+    ||L^-T L^-1 A z - z||^2 (its gradient from the adjoint of the
+    preconditioner solve). The loss falls, the iterations do not: IC(0) is
+    already at this pattern's iteration floor here. (Experiment as a test.)"""
+    A, L, g = small_graph(E=4, sigma=1.5, seed=31)
+    b = np.random.default_rng(4).standard_normal(g.n)
+    rng = np.random.default_rng(6)
+    zs_eval = [rng.choice([-1.0, 1.0], g.n) for _ in range(8)]
+
+    def solve_loss(Lv, z, want_grad=False):
+        Lx = (L[0], L[1], Lv)
+        U = oracle.transpose(*Lx)
+        az = oracle.spmv(*A, z)
+        _, Z = oracle.apply(Lx, U, az)
+        d = Z - z
+        if not want_grad:
+            return float(d @ d)
+        return float(d @ d), oracle.apply_adjoint(Lx, U, az, 2.0 * d)["dL"]
+
+    def grad(th, t):
+        zs = [rng.choice([-1.0, 1.0], g.n) for _ in range(4)]
+        return sum(solve_loss(th, z, True)[1] for z in zs) / len(zs)
+
+    l0 = np.mean([solve_loss(g.Lic, z) for z in zs_eval])
+    Lopt = _adam_on_values(g.Lic, grad, steps=150, lr=2e-3 * np.abs(g.Lic).mean(), keep_diag_positive=g.diag)
+    l1 = np.mean([solve_loss(Lopt, z) for z in zs_eval])
+    k0, k1 = _iters(A, g.Lic, L, b), _iters(A, Lopt, L, b)
+    print(f"solve loss {l0:.4e} -> {l1:.4e} ({100 * (l1 - l0) / l0:+.1f}%); PCG iterations {k0} -> {k1}")
+    assert l1 < 0.95 * l0
+    assert k1 >= k0 - 2
