@@ -71,3 +71,38 @@ def relerr(a, b):
     b = np.asarray(b, np.float64)
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def ulp_perturbed(A, seed):
+    """A with every stored value moved by one unit in the last place, up or
+    down at random, keeping A exactly symmetric (the upper triangle is drawn,
+    the lower mirrors it): a rounding-sized change that reaches every product
+    A p of a Krylov iteration."""
+    rp, ci, v = (np.asarray(a) for a in A)
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    lo, hi = np.minimum(rows, ci).astype(np.int64), np.maximum(rows, ci).astype(np.int64)
+    # one sign per unordered pair (i, j): a hash of the pair, the same from both sides
+    with np.errstate(over="ignore"):
+        h = lo * np.int64(0x27D4EB2F165667C5) + hi * np.int64(0x165667B19E3779F9) + np.int64(seed)
+    up = ((h >> 29) & 1).astype(bool)
+    vp = np.where(up, np.nextafter(v, np.inf), np.nextafter(v, -np.inf))
+    return rp, ci, vp
+
+
+def rounding_bars(A, b, k, kind, seed=7, factor=10.0):
+    """Tolerances of a GPU solve against the oracle derived from the iteration's
+    own sensitivity to rounding: the oracle run on ulp_perturbed(A) against the
+    oracle on A, (i) x after the same k steps, relative difference d, (ii) the
+    iterations to rtol 1e-8, difference dk. Returns (max(factor * d, 1e-12),
+    max(1, 2 * dk)): the GPU may differ from the oracle by `factor` times what
+    a one-ulp change of every entry of A causes (its summation orders differ
+    from the oracle's by a few ulps per sum), and stop within twice the
+    perturbed run's shift of the stopping step."""
+    Ap = ulp_perturbed(A, seed)
+    x0 = oracle.pcg_simple(A, b, kind, rtol=0.0, max_iter=k, max_replace=0)["x"]
+    x1 = oracle.pcg_simple(Ap, b, kind, rtol=0.0, max_iter=k, max_replace=0)["x"]
+    n = len(b)
+    k0 = oracle.pcg_simple(A, b, kind, rtol=1e-8, max_iter=20 * n)["iters"]
+    k1 = oracle.pcg_simple(Ap, b, kind, rtol=1e-8, max_iter=20 * n)["iters"]
+    return max(factor * relerr(x1, x0), 1e-12), max(1, 2 * abs(k1 - k0))
