@@ -384,8 +384,48 @@ def test_apply_f32_close_to_f64():
     z16 = oracle.apply_f32(L, U, r, 2)
     e32 = np.linalg.norm(z32 - z) / np.linalg.norm(z)
     e16 = np.linalg.norm(z16 - z) / np.linalg.norm(z)
-    assert 0 < e32 < 1e-5
-    assert e32 < e16 < 1e-1
+    # float arithmetic leaves errors of float's unit roundoff (2^-24 = 6e-8)
+    # times the solve's growth, and a BF16 factor (2^-9 = 2e-3) far more: an
+    # emulation that kept FP64 anywhere, or skipped the BF16 rounding, lands
+    # orders of magnitude lower
+    assert 1e-8 < e32 < 1e-5
+    assert 1e-4 < e16 < 1e-1
+    # the result is the float solve's, widened
+    for zz in (z32, z16):
+        assert np.array_equal(zz.astype(np.float32).astype(np.float64), zz)
+
+
+def test_apply_f32_exact_on_dyadic_factor():
+    """A factor whose values are powers of two (and sums of two) with an
+    integer right-hand side: every intermediate of both triangular solves is a
+    short dyadic rational, exact in float, so the float-emulated apply equals
+    the exact L^-T L^-1 r computed in rational arithmetic from the dense
+    factor, bit for bit."""
+    from fractions import Fraction
+    rng = np.random.default_rng(12)
+    n = 9
+    Ld = np.zeros((n, n))
+    for i in range(n):
+        Ld[i, i] = float(2 ** int(rng.integers(0, 3)))
+        for j in range(i):
+            if rng.random() < 0.45:
+                Ld[i, j] = float(rng.choice([-0.5, 0.25, -0.125, 0.75]))
+    L = dense_to_csr(Ld)
+    U = oracle.transpose(*L)
+    r = rng.integers(-8, 9, n).astype(np.float64)
+    F = [[Fraction(Ld[i, j]) for j in range(n)] for i in range(n)]
+    y = []
+    for i in range(n):
+        y.append((Fraction(r[i]) - sum(F[i][j] * y[j] for j in range(i))) / F[i][i])
+    z = [Fraction(0)] * n
+    for i in reversed(range(n)):
+        z[i] = (y[i] - sum(F[j][i] * z[j] for j in range(i + 1, n))) / F[i][i]
+    # the exact result is short enough for float (checked, so the test means
+    # what it says)
+    exact = np.array([float(v) for v in z])
+    assert all(Fraction(float(np.float32(v))) == v for v in z)
+    assert np.array_equal(oracle.apply_f32(L, U, r, 1), exact)
+    assert np.array_equal(oracle.apply(L, U, r)[1], exact)
 
 
 # ----------------------------------------------------------------- adjoint
