@@ -20,10 +20,13 @@
 //  * Latency: every item's metadata is one 16-byte record in schedule order,
 //    fetched one item ahead; indices, factor values, the diagonal block and
 //    the right-hand side are loaded before any wait; all dependencies are
-//    gathered in one round, and only while some are still pending do the
-//    lanes covering one pending row poll its columns (with a short backoff)
-//    before the pending ones are loaded again, so thousands of waiting waves
-//    do not flood the memory system and a ready input costs one round trip.
+//    gathered in one round. While some are still pending, the 16-column
+//    FP32 / BF16 solves load every pending one again each round (the round
+//    that sees the last input ends the wait); the others let the lanes
+//    covering one pending row poll it (with a short backoff) before the
+//    pending ones are loaded again, which keeps their memory traffic lower
+//    (measured: faster for the FP64 solves, slower for the 16-column FP32
+//    ones).
 //  * Lanes of a wave are (slot, column group): a lane owns CPL consecutive
 //    columns (1, or 2 from 8 columns up) and R / CPL lanes cover one gathered
 //    row of the row-major block, so every device-scope load and every publish
@@ -295,7 +298,34 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
         for (int cc = 0; cc < CPL; ++cc) xb[k][cc] = 0;
       }
     });
-    for (;;) {
+    if constexpr (kBC) {
+      // every pending entry is loaded again each round (one round trip per
+      // round, no sleep): the first round that sees the last input ends the
+      // wait, where polling one row and then reloading the rest costs a
+      // second round trip per dependency level
+      const long long t0w = wall_clock64();
+      for (;;) {
+        bool pend = false;
+#pragma unroll
+        for (int k = 0; k < QD; ++k) pend |= any_pending<TA, CPL>(xb[k]);
+        if (!__ballot(pend)) break;
+        const bool late = wall_clock64() - t0w > limit;
+        static_for<QD>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          if (any_pending<TA, CPL>(xb[k])) {
+            if (late) {
+              __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+              for (int cc = 0; cc < CPL; ++cc)
+                if (xb[k][cc] == Flag<TA>::kPending) xb[k][cc] = Flag<TA>::kCanonNaN;
+            } else {
+              load_elems<TA, CPL>(out + (int64_t)jj[k] * R + c0, xb[k]);
+            }
+          }
+        });
+      }
+    }
+    for (; !kBC;) {
       bool pend = false;
       int pk = 0;
 #pragma unroll

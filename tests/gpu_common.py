@@ -106,3 +106,15 @@ def rounding_bars(A, b, k, kind, seed=7, factor=10.0):
     k0 = oracle.pcg_simple(A, b, kind, rtol=1e-8, max_iter=20 * n)["iters"]
     k1 = oracle.pcg_simple(Ap, b, kind, rtol=1e-8, max_iter=20 * n)["iters"]
     return max(factor * relerr(x1, x0), 1e-12), max(1, 2 * abs(k1 - k0))
+
+
+def stop_agrees(k, k0, hist, rtol=1e-8, factor=2.0):
+    """A stopping step k agrees with the oracle's k0 when they differ by at
+    most one, or when the oracle's own recurrence residual (hist[j] =
+    ||r_j|| / ||b||) stays within `factor` * rtol at every step between them:
+    near rtol the recurrence residual moves by tens of percent from one step
+    to the next, so two runs whose iterates differ only by rounding may cross
+    rtol anywhere on such a plateau."""
+    if abs(k - k0) <= 1:
+        return True
+    return all(hist[j] <= factor * rtol for j in range(min(k, k0), max(k, k0) + 1) if j < len(hist))

@@ -19,6 +19,7 @@ import torch
 
 import oracle
 import paper_2412_07127_amd as pkg
+import gpu_common
 from gpu_common import relerr
 from synth import body_load, build_workload, q1_elasticity, traction_loads
 
@@ -144,18 +145,11 @@ def sample_err(x, g, case, k=None):
 
 
 def stop_agrees(k, c, rtol=1e-8):
-    """The stopping step k agrees with the oracle's k0 when they differ by at
-    most one, or when the oracle's own recurrence residual stays within a
-    factor 2 of rtol at every step between them. Near rtol the recurrence
-    residual jumps by tens of percent from one step to the next (the oracle's
-    load case 0 reads 1.06e-8, 1.14e-8, 1.64e-8, 1.36e-8, 1.23e-8, 1.06e-8,
-    9.3e-9 over steps 799-805), so two runs whose iterates agree to 1e-11 can
-    cross rtol anywhere on such a plateau."""
-    k0 = c["iters"]
-    if abs(k - k0) <= 1:
-        return True
-    h = c["relres_history"]
-    return all(h[j] <= 2 * rtol for j in range(min(k, k0), max(k, k0) + 1) if j < len(h))
+    """gpu_common.stop_agrees against a stored oracle case (the oracle's load
+    case 0 reads 1.06e-8, 1.14e-8, 1.64e-8, 1.36e-8, 1.23e-8, 1.06e-8, 9.3e-9
+    over steps 799-805: a plateau on which runs that agree to 1e-11 may stop
+    at any step)."""
+    return gpu_common.stop_agrees(k, c["iters"], c["relres_history"], rtol)
 
 
 # x of two FP64 runs of the same steps that differ only in the order of their

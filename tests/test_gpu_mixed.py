@@ -17,7 +17,7 @@ import torch
 
 import oracle
 import paper_2412_07127_amd as pkg
-from gpu_common import oracle_factor, relerr, workload_problem
+from gpu_common import oracle_factor, relerr, stop_agrees, workload_problem
 from synth import traction_loads
 
 pytestmark = pytest.mark.gpu
@@ -168,8 +168,10 @@ def _pcg_columns(ctx, key, E, dt, cols, rtol=1e-8):
 def test_multi_rhs_reduced_precision_pcg(ctx, ctx_unfused, key, E, dt, fused):
     """16 load cases at once with the factor in FP32 / BF16 (the headline's
     arithmetic, at sizes the oracle finishes in seconds). Per column:
-      * the oracle's float-emulated PCG on the same column converges in about the
-        same number of steps;
+      * the oracle's float-emulated PCG on the same column stops at an agreeing
+        step (within one, or anywhere on the plateau where the oracle's own
+        recurrence residual stays within 2 rtol: the two sides round the
+        preconditioner's sums in different orders);
       * after 3 steps the iterates agree to the apply's bound times the growth of
         three steps;
       * the converged x is within 1e-5 of the FP64 oracle's converged x, and the
@@ -183,14 +185,14 @@ def test_multi_rhs_reduced_precision_pcg(ctx, ctx_unfused, key, E, dt, fused):
     X3, i3 = c.solve(A, P, torch.from_numpy(B).cuda(), rtol=0.0, max_iter=3, max_replace=0, block_width=16)
     X3 = X3.cpu().numpy()
     for k in cols:
-        ref = _oracle_pcg(key, k, prec, rtol=1e-8)
+        ref = _oracle_pcg(key, k, prec, rtol=1e-8, history=True)
         ref64 = _oracle_pcg(key, k, 0, rtol=1e-8)
         r3 = _oracle_pcg(key, k, prec, rtol=0.0, max_iter=3, max_replace=0)
         assert info[k]["status"] == 0 and info[k]["true_relres"] <= 1e-8
         worst["dk"] = max(worst["dk"], abs(info[k]["iters"] - ref["iters"]))
         worst["e3"] = max(worst["e3"], relerr(X3[:, k], r3["x"]))
         worst["e64"] = max(worst["e64"], relerr(Xh[:, k], ref64["x"]))
-        assert abs(info[k]["iters"] - ref["iters"]) <= max(2, int(0.02 * ref["iters"]))
+        assert stop_agrees(info[k]["iters"], ref["iters"], ref["hist"]), (k, info[k]["iters"], ref["iters"])
     print(f"{key} {dt} fused={fused}: max |dk| {worst['dk']}, 3-step |dx|/|x| {worst['e3']:.2e}, "
           f"converged vs FP64 oracle {worst['e64']:.2e}")
     assert worst["e3"] <= 10 * APPLY_TOL[dt]
