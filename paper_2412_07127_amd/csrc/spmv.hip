@@ -143,8 +143,10 @@ template <int SLOTS> struct GrpDepth {
   static constexpr int v = (88 + SLOTS - 1) / SLOTS > 11 ? 11 : (88 + SLOTS - 1) / SLOTS;
 };
 
-// At least three waves per SIMD (at most 168 VGPRs).
-template <int R, int SLOTS, int CPL, int QD = GrpDepth<SLOTS>::v>
+// At least three waves per SIMD (at most 168 VGPRs). NT: A's values are
+// loaded nontemporal, so the stream of A (read once) does not push the x rows
+// out of the L2 between their gathers.
+template <int R, int SLOTS, int CPL, bool NT, int QD = GrpDepth<SLOTS>::v>
 __global__ __launch_bounds__(kBlock, 3) void k_spmv_grp(const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                      int64_t ngroups, const SpGroup *__restrict__ grec,
                                                      const double *__restrict__ x, double *__restrict__ y,
@@ -182,7 +184,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_spmv_grp(const int32_t *__restric
       jj[k] = ci[base + qc];
 #pragma unroll
       for (int u = 0; u < GMAX; ++u)  // rows >= sz: unused
-        vv[k][u] = v[base + (u < sz ? u : sz - 1) * m + qc] * keep;
+        vv[k][u] = (NT ? __builtin_nontemporal_load(v + base + (u < sz ? u : sz - 1) * m + qc)
+                       : v[base + (u < sz ? u : sz - 1) * m + qc]) * keep;
     }
     __builtin_amdgcn_sched_barrier(0);
     double acc[GMAX][CPL];
@@ -247,15 +250,20 @@ int launch_grp(const int32_t *ci, const double *v, int64_t ngroups, const SpGrou
   constexpr int GPB = kBlock / (SLOTS * (R / CPL));
   // Short chunks keep the groups in flight on one XCD close together, so its
   // L2 serves more of the neighbouring x gathers (measured best per width).
+  // At 16 columns: one pass per block with A's values nontemporal (100^3,
+  // counters: 3.76 GB moved per launch against 7.29 GB with 16 passes and A
+  // cached, 1.30 against 1.33 ms; one pass with A cached moves 3.58 GB but
+  // takes 1.53 ms).
   static const int iters_env = std::getenv("ICPCG_SPMVG_ITERS") ? std::atoi(std::getenv("ICPCG_SPMVG_ITERS")) : 0;
-  const int ITERS = iters_env > 0 ? iters_env : (R >= 16 ? 16 : R >= 8 ? 8 : R >= 4 ? 2 : 1);
+  constexpr bool NT = R >= 16;
+  const int ITERS = iters_env > 0 ? iters_env : (R >= 16 ? 1 : R >= 8 ? 8 : R >= 4 ? 2 : 1);
   int64_t nb = (ngroups + GPB * ITERS - 1) / (GPB * ITERS);
   if (nb < 1) nb = 1;
   const int64_t chunk = (ngroups + nb - 1) / nb;
   nb = (ngroups + chunk - 1) / chunk;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, CPL>), dim3((unsigned)nb), dim3(kBlock), 0, s, ci, v, ngroups, grec, x, y,
-                     chunk, partials ? active : nullptr);
+  hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, CPL, NT>), dim3((unsigned)nb), dim3(kBlock), 0, s, ci, v, ngroups, grec, x,
+                     y, chunk, partials ? active : nullptr);
   ICPCG_HIP_TRY(hipGetLastError());
   if (!partials) return ICPCG_OK;
   // p^T w for alpha: one deterministic pass over p = x and w = y
