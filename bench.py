@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
     ap.add_argument("--skip-single", action="store_true", help="omit the single-RHS variants")
+    ap.add_argument("--skip-150", action="store_true", help="omit the 150^3 inference workload")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--kernels-only", action="store_true",
                     help="factor, then only the per-kernel launches at the headline shape and a copy of known "
@@ -225,43 +226,108 @@ def errors_vs_oracle(E, sigma, n, rtol, singles, outs, torch):
     columns. None for other workloads."""
     if (E, sigma, rtol) != (100, 2.0, 1e-8):
         return None
-    path = os.path.join(ROOT, "tests", "golden", "q1_100_oracle.json")
-    try:
-        g = json.load(open(path))
-        with np.load(os.path.join(ROOT, "tests", "golden", "q1_100_oracle_x.npz")) as z:
-            xs = {k: z[k] for k in z.files}
-    except OSError:
+    g = load_golden(100)
+    if g is None or g["n"] != n:
         return None
-    if g["n"] != n:
-        return None
-    idx = torch.as_tensor(g["sample_index"], dtype=torch.long, device="cuda")
-
-    def rel(x, case, k=None):
-        c = g["cases"][case]
-        k = c["iters"] if k is None else k
-        lo, hi = c["x_window_steps"]
-        if not lo <= k <= hi:
-            return None
-        ref = torch.as_tensor(xs[case][k - lo], dtype=torch.float64, device="cuda")
-        return float(torch.linalg.norm(x[idx] - ref) / torch.linalg.norm(ref))
-
     out = {}
     for name, (X, info) in singles.items():
         if name in ("fp64", "fp32_L", "bf16_L"):
-            out[name] = rel(X, "body", info["iters"] if name == "fp64" else None)
+            out[name] = golden_rel(g, X, "body", torch, info["iters"] if name == "fp64" else None)
             if name == "fp64":
                 out["fp64_iters_minus_oracle"] = info["iters"] - g["cases"]["body"]["iters"]
     for name, (X, infos) in outs.items():
         if name.startswith("multi16") and X.dim() == 2:
             for c in (0, 1):
-                case = f"traction{c}"
-                k = infos[c]["iters"] if name == "multi16_fp64_L" else None
-                out[f"{name}_col{c}"] = rel(X[:, c].contiguous(), case, k)
-                if name == "multi16_fp64_L":
-                    out[f"{name}_col{c}_iters_minus_oracle"] = k - g["cases"][case]["iters"]
+                out[f"{name}_col{c}"] = golden_rel(g, X[:, c].contiguous(), f"traction{c}", torch)
     out["oracle_iters"] = {k: v["iters"] for k, v in g["cases"].items()}
     out["note"] = ("relative 2-norm error on every 997th entry; FP64 runs at equal step count, reduced-precision "
                    "factors against the oracle's converged FP64 solution")
+    return out
+
+def load_golden(E):
+    """The stored FP64 oracle solves of the E^3 workload (tests/golden, written
+    by a script that calls only the oracle), or None."""
+    base = os.path.join(ROOT, "tests", "golden", f"q1_{E}_oracle")
+    try:
+        g = json.load(open(base + ".json"))
+        with np.load(base + "_x.npz") as z:
+            g["x"] = {k: z[k] for k in z.files}
+    except OSError:
+        return None
+    return g
+
+
+def golden_rel(g, x, case, torch, k=None):
+    """Relative error of x on the stored sample against the oracle's x after k
+    steps (default: the oracle's converged count); None outside the window."""
+    c = g["cases"][case]
+    k = c["iters"] if k is None else k
+    lo, hi = c["x_window_steps"]
+    if not lo <= k <= hi:
+        return None
+    idx = torch.as_tensor(g["sample_index"], dtype=torch.long, device="cuda")
+    ref = torch.as_tensor(g["x"][case][k - lo], dtype=torch.float64, device="cuda")
+    return float(torch.linalg.norm(x[idx] - ref) / torch.linalg.norm(ref))
+
+
+def inference_150(ctx, torch, rtol):
+    """The 150^3 inference workload (10,260,450 DOF, 820M stored entries,
+    sigma 1.5; 16 traction load cases): IC(0) on the GPU (P-time), one FP64
+    solve of load case 0 (the comparison: 16 such sequential solves), then one
+    16-RHS step with the factor applied in FP32 at the autotuned width, steps
+    replayed as a hipGraph; load cases 0 and 1 against the stored FP64 oracle
+    solves when present (FP64 at its own step count, the batch's columns
+    against the oracle's converged x)."""
+    import paper_2412_07127_amd as pkg
+    from synth import build_workload
+    t = time.perf_counter()
+    prob, B = build_workload("q1_150_loads16")
+    log(f"inference workload: generated E=150 n={prob.n} nnz={prob.nnz} ({time.perf_counter() - t:.1f} s)")
+    A = pkg.CSR.from_numpy(prob.row_ptr, prob.col, prob.val, "cuda")
+    M = ctx.matrix(A)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    L, finfo = ctx.factor(A)
+    torch.cuda.synchronize()
+    p_time = time.perf_counter() - t
+    P64 = ctx.prec(L, "f64")
+    P32 = ctx.prec(L, "f32")
+    del L
+    Bt = torch.from_numpy(B).cuda()
+    b0 = Bt[:, 0].contiguous()
+    ctx.solve(M, P64, b0, rtol=rtol, max_iter=5)  # code objects and workspace, untimed
+    log("inference workload: one FP64 solve of load case 0 ...")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x0, i0 = ctx.solve(M, P64, b0, rtol=rtol)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t
+    log(f"inference workload: FP64 {t64:.3f} s, {i0[0]['iters']} it; autotune and one 16-RHS step ...")
+    tune = ctx.autotune(M, P32, 16)
+    ctx.solve(M, P32, Bt, rtol=rtol, use_graph=True, max_iter=5)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    X, info = ctx.solve(M, P32, Bt, rtol=rtol, use_graph=True)
+    torch.cuda.synchronize()
+    t16 = time.perf_counter() - t
+    iters = [i["iters"] for i in info]
+    out = dict(workload="Q1 elasticity 150^3 elements, sigma=1.5, 16 traction load cases", n=prob.n,
+               nnz_A=prob.nnz, p_time_s=round(p_time, 4), alpha=finfo["alpha"],
+               fp64_single_s=round(t64, 4), fp64_single_iters=i0[0]["iters"],
+               step16_s=round(t16, 4), per_rhs_s=round(t16 / 16, 4), rhs_per_s=round(16 / t16, 4),
+               iters_min=min(iters), iters_max=max(iters), true_relres_max=max(i["true_relres"] for i in info),
+               block_width=tune["block_width"],
+               speedup_vs_16_sequential_fp64=round(16 * t64 / t16, 3))
+    g = load_golden(150)
+    if g is not None and g["n"] == prob.n:
+        out["err_vs_oracle"] = dict(
+            fp64_col0=golden_rel(g, x0, "traction0", torch, i0[0]["iters"]),
+            fp64_col0_iters_minus_oracle=i0[0]["iters"] - g["cases"]["traction0"]["iters"],
+            step16_col0=golden_rel(g, X[:, 0].contiguous(), "traction0", torch),
+            step16_col1=golden_rel(g, X[:, 1].contiguous(), "traction1", torch))
+    log(f"inference workload: {out}")
+    del A, M, P64, P32, Bt, X, x0
+    torch.cuda.empty_cache()
     return out
 
 
@@ -467,10 +533,25 @@ def main():
         kernels_b = {k_: dict(ms=round(kt_b[k_] * 1e3, 4), algorithmic_GBs=round(b_ / kt_b[k_] / 1e9, 1))
                      for k_, b_ in (("spmv", spmv_b), ("trsv_L", trsvLb), ("trsv_U_rz", trsvUb))}
         log(f"block multicolour kernels: {kernels_b}")
-    dom = max(kernels, key=lambda k_: kernels[k_]["s"])
-    roof = dict(bound="hbm", kernel=dom, achieved=round(kernels[dom]["gbs"], 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=round(kernels[dom]["gbs"] / PEAK_HBM_GBS, 4), traffic=recorded_traffic(dom),
-                algorithmic_bytes_per_launch=kernels[dom]["bytes"], launch_ms=round(kernels[dom]["s"] * 1e3, 4))
+    # the same kernels inside the headline's PCG step: 64 eager steps of the
+    # headline solve (16 columns, FP32 factor) with events at every phase
+    # boundary on the library's stream (graph replay runs the same kernels)
+    log("in-step phase timing: 64 eager steps of the headline solve ...")
+    ctx.step_timing(True)
+    ctx.solve(M, P32, Bt, rtol=0.0, max_iter=64, max_replace=0, block_width=R)
+    ph = ctx.step_timing_get()
+    ctx.step_timing(False)
+    log(f"in-step phases (ms): {ph}")
+    in_step = {"spmv": ph["spmv"] * 1e-3, "trsv_L": ph["trsv_L"] * 1e-3, "trsv_U_rz": ph["trsv_U"] * 1e-3}
+    for k_ in kernels:
+        kernels[k_]["in_step_s"] = in_step[k_]
+    # the roofline's kernel: the largest of the three inside the step
+    dom = max(kernels, key=lambda k_: kernels[k_]["in_step_s"])
+    gbs_in = kernels[dom]["bytes"] / kernels[dom]["in_step_s"] / 1e9
+    roof = dict(bound="hbm", kernel=dom, achieved=round(gbs_in, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(gbs_in / PEAK_HBM_GBS, 4), traffic=recorded_traffic(dom),
+                algorithmic_bytes_per_launch=kernels[dom]["bytes"], launch_ms=round(kernels[dom]["in_step_s"] * 1e3, 4),
+                timing="mean of 64 in-step launches (events at the step's phase boundaries)")
 
     # the learned correction at this scale: one forward (inference) and one
     # loss + gradient pass (a training step's work) over nnz(L) edges
@@ -508,6 +589,10 @@ def main():
         log(f"cpu baseline: {cpu['sample']}")
         cpu = {k_: cpu[k_] for k_ in ("value", "unit", "cores", "kind", "sample", "single_thread", "multi_thread",
                                       "nproc", "factor_s")}
+
+    inf150 = None
+    if not args.skip_150:
+        inf150 = inference_150(ctx, torch, args.rtol)
 
     fp64 = variants.get("fp64")
     out = {
@@ -549,19 +634,18 @@ def main():
                                    supernode_levels_U=pinfo_c["nsn_levels_U"]),
         "variants": variants,
         "gnn_correction": gnn,
-        "kernels": {k_: dict(ms=round(v["s"] * 1e3, 4), algorithmic_GBs=round(v["gbs"], 1),
-                             bytes=v["bytes"], frac_hbm_peak=round(v["gbs"] / PEAK_HBM_GBS, 4))
+        "kernels": {k_: dict(ms_in_step=round(v["in_step_s"] * 1e3, 4),
+                             algorithmic_GBs_in_step=round(v["bytes"] / v["in_step_s"] / 1e9, 1),
+                             frac_hbm_peak_in_step=round(v["bytes"] / v["in_step_s"] / 1e9 / PEAK_HBM_GBS, 4),
+                             ms_standalone=round(v["s"] * 1e3, 4), algorithmic_GBs_standalone=round(v["gbs"], 1),
+                             bytes=v["bytes"])
                     for k_, v in kernels.items()},
+        "step_phases_ms": {k_: round(v, 4) for k_, v in ph.items() if k_ != "steps"},
         "err_vs_oracle": err,
+        "inference_150": inf150,
     }
-    m64 = variants.get("multi16_fp64_L")
     if fp64:
         out["speedup_per_rhs_vs_fp64_single"] = round(fp64["cg_s"] / (step_s / args.nrhs), 3)
-        if m64:
-            # batching alone (FP64 factor, 16 columns vs one) and precision alone
-            # (FP32 vs FP64 factor, both 16 columns)
-            out["speedup_per_rhs_batching_fp64_L"] = round(fp64["cg_s"] / m64["per_rhs_s"], 3)
-            out["speedup_per_rhs_fp32_vs_fp64_L_16"] = round(m64["per_rhs_s"] / (step_s / args.nrhs), 3)
     print(json.dumps(out), flush=True)
 
 

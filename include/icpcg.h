@@ -377,6 +377,21 @@ icpcg_status icpcg_solve_mat(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_pre
                              const double *B, double *X, int64_t nrhs,
                              const icpcg_solve_opts *opts, icpcg_col_info *info);
 
+/* Per-phase timing of PCG steps (the CG part of supplementary section 2's
+ * time model T = T_p + l t_cg, split by phase). With enable != 0 the context
+ * records events on its stream at the phase boundaries of the next eager
+ * steps (use_graph = 0; graph-replayed steps are not timed), up to 64 steps
+ * from the call on; enable = 0 stops recording. icpcg_step_timing_get
+ * synchronizes the stream and writes ms[6] (host), the mean over the recorded
+ * steps of each phase in ms: the forward solve; the backward solve (with r^T z
+ * and beta where the solve forms them, else with their pass); the p update
+ * (with the re-arming of y and z); w = A p; p^T w and alpha (empty where the
+ * SpMV forms p^T w); the x and r update with ||r||. *steps (host) receives
+ * the number of steps recorded (0: ms all 0). Errors: ICPCG_E_INVALID (null
+ * arguments), ICPCG_E_DEVICE. */
+icpcg_status icpcg_step_timing(icpcg_ctx *ctx, int enable);
+icpcg_status icpcg_step_timing_get(icpcg_ctx *ctx, double *ms, int64_t *steps);
+
 /* ------------------------------------------------ multicolour ordering */
 
 /* A symmetric permutation that exposes parallelism to the triangular solves

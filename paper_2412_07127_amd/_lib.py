@@ -101,6 +101,8 @@ def load():
         "icpcg_mat_spmv": ([P, P, P, P, i64], st),
         "icpcg_solve_mat": ([P, P, P, P, P, i64, C.POINTER(SolveOpts), C.POINTER(ColInfo)], st),
         "icpcg_autotune": ([P, P, P, i64, C.POINTER(TuneInfo)], st),
+        "icpcg_step_timing": ([P, st], st),
+        "icpcg_step_timing_get": ([P, P, C.POINTER(i64)], st),
         "icpcg_color_order": ([P, C.POINTER(Csr), C.c_uint64, P, C.POINTER(C.c_int32)], st),
         "icpcg_block_color_order": ([P, C.POINTER(Csr), P, C.c_int32, P, C.POINTER(C.c_int32)], st),
         "icpcg_permute_matrix": ([P, C.POINTER(Csr), P, P, P, P], st),

@@ -230,6 +230,7 @@ icpcg_status icpcg_destroy(icpcg_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->step_exec) (void)hipGraphExecDestroy(ctx->step_exec);
   if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
+  for (hipEvent_t e : ctx->tev) (void)hipEventDestroy(e);
   if (ctx->ws.host_flags) (void)hipHostFree(ctx->ws.host_flags);
   delete ctx;
   return ICPCG_OK;
@@ -242,6 +243,41 @@ icpcg_status icpcg_set_stream(icpcg_ctx *ctx, void *stream) {
 }
 
 const char *icpcg_last_error(const icpcg_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+icpcg_status icpcg_step_timing(icpcg_ctx *ctx, int enable) {
+  if (!ctx) return ICPCG_E_INVALID;
+  if (enable && ctx->tev.empty()) {
+    ctx->tev.resize((size_t)icpcg_ctx::kPhaseMarks * icpcg_ctx::kTimedSteps, nullptr);
+    for (hipEvent_t &e : ctx->tev) {
+      const hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return fail(ctx, ICPCG_E_DEVICE, std::string("step_timing: ") + hipGetErrorString(r));
+    }
+  }
+  ctx->timing = enable != 0;
+  if (enable) ctx->tsteps = 0;
+  return ICPCG_OK;
+}
+
+icpcg_status icpcg_step_timing_get(icpcg_ctx *ctx, double *ms, int64_t *steps) {
+  if (!ctx || !ms || !steps) return ICPCG_E_INVALID;
+  constexpr int NP = icpcg_ctx::kPhaseMarks - 1;
+  for (int m = 0; m < NP; ++m) ms[m] = 0.0;
+  *steps = ctx->tsteps;
+  if (ctx->tsteps == 0) return ICPCG_OK;
+  const hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(ctx, ICPCG_E_DEVICE, std::string("step_timing_get: ") + hipGetErrorString(e));
+  for (int64_t k = 0; k < ctx->tsteps; ++k) {
+    for (int m = 0; m < NP; ++m) {
+      float t = 0.f;
+      const hipError_t r = hipEventElapsedTime(&t, ctx->tev[k * icpcg_ctx::kPhaseMarks + m],
+                                               ctx->tev[k * icpcg_ctx::kPhaseMarks + m + 1]);
+      if (r != hipSuccess) return fail(ctx, ICPCG_E_DEVICE, std::string("step_timing_get: ") + hipGetErrorString(r));
+      ms[m] += t;
+    }
+  }
+  for (int m = 0; m < NP; ++m) ms[m] /= (double)ctx->tsteps;
+  return ICPCG_OK;
+}
 
 icpcg_status icpcg_tril_nnz(icpcg_ctx *ctx, const icpcg_csr *A, int64_t *nnz_lower) {
   if (!ctx || !valid_csr_args(A) || !nnz_lower) return fail(ctx, ICPCG_E_INVALID, "tril_nnz: bad arguments");
@@ -664,30 +700,56 @@ int spmv_pass(const icpcg_csr *A, const PassBuffers &b, const double *x, double 
 // columns), p = z + beta p, w = A p with p'w, then alpha, x, r and ||r||.
 // Queued steps return at once when no column is active.
 int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const PassBuffers &b, int R,
-                  int64_t max_iter, int count, hipStream_t s) {
+                  int64_t max_iter, int count, hipStream_t s, bool timed = false) {
   const int64_t n = A->n;
   const bool lo = P->dtype != ICPCG_F64;
   SolveFlags *fl = dev_flags(ctx);
   int *err = &fl->err;
   const int *act = &fl->n_active;
   int st;
+  // phase boundaries of the step (icpcg_step_timing; eager steps only)
+  auto mark = [&](int m) -> int {
+    if (!timed || ctx->tsteps >= icpcg_ctx::kTimedSteps) return ICPCG_OK;
+    ICPCG_HIP_TRY(hipEventRecord(ctx->tev[ctx->tsteps * icpcg_ctx::kPhaseMarks + m], s));
+    return ICPCG_OK;
+  };
   for (int k = 0; k < count; ++k) {
+    if ((st = mark(0))) return st;
     if (P->kind != ICPCG_PREC_FACTOR) {
       if ((st = pcg_diag_apply(n, R, b.r, P->kind == ICPCG_PREC_JACOBI ? P->diag.as<double>() : nullptr,
                                static_cast<double *>(b.z), act, s)))
         return st;
     } else {
       if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err, act))) return st;
+      if ((st = mark(1))) return st;
       // the backward solve also forms r^T z and beta where that pays
       const RzDot rz = trsv_fuses_rz(P, R, ctx->dev) ? RzDot{b.r, b.partials, b.cols, fl} : RzDot{};
       if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err, act, rz))) return st;
     }
+    if (P->kind != ICPCG_PREC_FACTOR && (st = mark(1))) return st;
     if (!(P->kind == ICPCG_PREC_FACTOR && trsv_fuses_rz(P, R, ctx->dev)) &&
         (st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, b.cols, fl, s)))
       return st;
+    if ((st = mark(2))) return st;
     if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.cols, fl, s))) return st;
-    if ((st = spmv_pass(A, b, b.p, b.w, R, s, b.partials, b.cols, act))) return st;
+    if ((st = mark(3))) return st;
+    if (b.grec) {
+      // w = A p, then p^T w and alpha in their own pass (what the grouped
+      // SpMV launch does with partials, split here at a phase boundary)
+      if ((st = spmv_grouped(A->col, A->val, b.ngroups, b.grec, n, b.p, b.w, R, spmv_grouped_default_slots(R), s,
+                             nullptr, nullptr, act)))
+        return st;
+      if ((st = mark(4))) return st;
+      if ((st = pcg_dot_pw(n, R, b.p, b.w, b.partials, b.cols, fl, s))) return st;
+    } else {
+      // the row kernel forms p^T w in its epilogue (the p^T w phase is empty)
+      if ((st = spmv_pass(A, b, b.p, b.w, R, s, b.partials, b.cols, act))) return st;
+      if ((st = mark(4))) return st;
+    }
+    if ((st = mark(5))) return st;
     if ((st = pcg_update_xr(n, R, b.X, b.r, b.p, b.w, b.partials, b.cols, max_iter, fl, s))) return st;
+    if ((st = mark(6))) return st;
+    if (timed && ctx->tsteps < icpcg_ctx::kTimedSteps) ++ctx->tsteps;
   }
   return ICPCG_OK;
 }
@@ -781,7 +843,7 @@ int run_pass(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const Pass
     }
     if (exec)
       ICPCG_HIP_TRY(hipGraphLaunch(exec, s));
-    else if ((st = enqueue_steps(ctx, A, P, b, R, max_iter, every, s)))
+    else if ((st = enqueue_steps(ctx, A, P, b, R, max_iter, every, s, ctx->timing)))
       return st;
     steps += every;
   }

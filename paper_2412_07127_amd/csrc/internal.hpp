@@ -100,6 +100,12 @@ struct icpcg_ctx {
     double ms[5];
   };
   std::vector<Tune> tunes;
+  // per-phase timing of eager PCG steps (icpcg_step_timing): events recorded
+  // at the kPhaseMarks phase boundaries of the first kTimedSteps steps
+  static constexpr int kPhaseMarks = 7, kTimedSteps = 64;
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  int64_t tsteps = 0;
 };
 
 // One schedule position of a triangular solve: the supernode's first row a,

@@ -263,7 +263,7 @@ int launch_grp(const int32_t *ci, const double *v, int64_t ngroups, const SpGrou
   nb = (ngroups + chunk - 1) / chunk;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL((k_spmv_grp<R, SLOTS, CPL, NT>), dim3((unsigned)nb), dim3(kBlock), 0, s, ci, v, ngroups, grec, x,
-                     y, chunk, partials ? active : nullptr);
+                     y, chunk, active);
   ICPCG_HIP_TRY(hipGetLastError());
   if (!partials) return ICPCG_OK;
   // p^T w for alpha: one deterministic pass over p = x and w = y

@@ -298,6 +298,23 @@ class Context:
                     ms_per_step={w: info.ms_per_step[i] for i, w in enumerate((1, 2, 4, 8, 16))
                                  if info.ms_per_step[i] > 0})
 
+    STEP_PHASES = ("trsv_L", "trsv_U", "update_p", "spmv", "pw", "update_xr")
+
+    def step_timing(self, enable: bool = True):
+        """Record the phase durations of the next eager PCG steps (up to 64)."""
+        self._bind()
+        self._check(self.lib.icpcg_step_timing(self.h, int(bool(enable))))
+
+    def step_timing_get(self) -> dict:
+        """Mean ms per phase over the recorded steps, and their count."""
+        self._bind()
+        ms = (C.c_double * len(self.STEP_PHASES))()
+        steps = C.c_int64(0)
+        self._check(self.lib.icpcg_step_timing_get(self.h, ms, C.byref(steps)))
+        out = {k: ms[i] for i, k in enumerate(self.STEP_PHASES)}
+        out["steps"] = steps.value
+        return out
+
     def sync(self):
         self._check(self.lib.icpcg_sync(self.h))
 

@@ -1,11 +1,13 @@
-"""Writes tests/golden/q1_100_oracle.json and q1_100_oracle_x.npz: FP64 oracle
-solves of the 100^3 elasticity workload (3,060,300 DOF, sigma 2.0, seed 1003),
-for the full-size GPU parity tests and the benchmark's error-against-oracle
-figure.
+"""Writes tests/golden/q1_<E>_oracle.json and q1_<E>_oracle_x.npz: FP64 oracle
+solves of a full-size elasticity workload, for the full-size GPU parity tests
+and the benchmark's error-against-oracle figures:
+  * E = 100 (default): 3,060,300 DOF, sigma 2.0, seed 1003; the body load +
+    noise of seed 2003 and load cases 0 and 1 of the sixteen traction columns
+    of seed 2004;
+  * E = 150 (argument "150"): 10,260,450 DOF, sigma 1.5, seed 1004; load cases
+    0 and 1 of its sixteen traction columns (seed 2004).
 
-Calls only the oracle and the input generator. Per right-hand side (the body
-load + noise of seed 2003, and load cases 0 and 1 of the sixteen traction
-columns of seed 2004):
+Calls only the oracle and the input generator. Per right-hand side:
   * JSON: the converged solve (rtol 1e-8, true residual checked): status, k0,
     relative and true residual, the recurrence residual of every step;
   * NPZ: x sampled every 997th entry after every step k0 - W .. k0 + W
@@ -14,7 +16,7 @@ columns of seed 2004):
     count.
 The factor (IC(0) with the global shift rule) is computed once; the solves run
 in forked worker processes that share it, one thread each. Takes about 15
-minutes on 8 cores.
+minutes (E = 100) and about an hour (E = 150) on 8 cores.
 """
 
 import json
@@ -31,14 +33,19 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 from synth import WORKLOADS, build_workload, traction_loads  # noqa: E402
 
-OUT = os.path.join(HERE, "q1_100_oracle.json")
-OUT_X = os.path.join(HERE, "q1_100_oracle_x.npz")
 STRIDE = 997
 TRACTION_COLUMNS = (0, 1)
 W = 8
-# the recording run goes to K_HI steps and keeps K_LO .. K_HI; every k0 +- W must
-# fall inside (asserted)
-K_LO, K_HI = 760, 850
+# per workload: the generator's name, whether the body-load column is solved,
+# and the recording window K_LO .. K_HI (the run goes to K_HI steps; every
+# k0 +- W must fall inside, asserted)
+CASES = {100: dict(name="q1_100", body=True, k_lo=760, k_hi=850),
+         150: dict(name="q1_150_loads16", body=False, k_lo=960, k_hi=1080)}
+E_RUN = int(sys.argv[1]) if len(sys.argv) > 1 else 100
+CFG = CASES[E_RUN]
+OUT = os.path.join(HERE, f"q1_{E_RUN}_oracle.json")
+OUT_X = os.path.join(HERE, f"q1_{E_RUN}_oracle_x.npz")
+K_LO, K_HI = CFG["k_lo"], CFG["k_hi"]
 
 _S = {}  # matrix, factor and right-hand sides, inherited by the forked workers
 
@@ -56,14 +63,14 @@ def _solve(job):
 
 def main():
     t0 = time.time()
-    prob, b = build_workload("q1_100")
+    prob, b = build_workload(CFG["name"])
     A = (prob.row_ptr, prob.col, prob.val)
     st, L, alpha, restarts, minpiv = oracle.ic0_shifted(*A)
     assert st == oracle.OK
     U = oracle.transpose(*L)
     seed_t = WORKLOADS["q1_150_loads16"]["seed_b"]
-    B = traction_loads(100, max(TRACTION_COLUMNS) + 1, seed_t)
-    rhs = {"body": b}
+    B = traction_loads(E_RUN, max(TRACTION_COLUMNS) + 1, seed_t)
+    rhs = {"body": b} if CFG["body"] else {}
     for c in TRACTION_COLUMNS:
         rhs[f"traction{c}"] = np.ascontiguousarray(B[:, c])
     idx = np.arange(0, prob.n, STRIDE)
@@ -89,12 +96,12 @@ def main():
             true_relres=r["true_relres"], x_norm=float(np.linalg.norm(r["x"])),
             relres_history=r["hist"].tolist(), x_window_steps=[k0 - W, k0 + W])
     out = dict(
-        what="FP64 oracle on the 100^3 Q1 elasticity workload (sigma 2.0, seed 1003): IC(0) with the global "
+        what=f"FP64 oracle on the {E_RUN}^3 Q1 elasticity workload ({CFG['name']}): IC(0) with the global "
              "shift rule, then PCG to rtol 1e-8 (true residual checked) from x0 = 0; the iterates on every "
              f"{STRIDE}th entry after steps k0 - {W} .. k0 + {W} are in q1_100_oracle_x.npz (key = case name, "
              "row = step - (k0 - W))",
-        rhs={"body": "body load (0,0,-1) + N(0, 0.1^2) noise, seed 2003",
-             **{f"traction{c}": f"load case {c} of traction_loads(100, 16, {seed_t})" for c in TRACTION_COLUMNS}},
+        rhs={**({"body": "body load (0,0,-1) + N(0, 0.1^2) noise, seed 2003"} if CFG["body"] else {}),
+             **{f"traction{c}": f"load case {c} of traction_loads({E_RUN}, 16, {seed_t})" for c in TRACTION_COLUMNS}},
         n=prob.n, nnz=prob.nnz, alpha=alpha, restarts=restarts, min_pivot=minpiv,
         sample_stride=STRIDE, sample_index=idx.tolist(), window=W, cases=cases, seconds=time.time() - t0)
     np.savez(OUT_X, **xw)

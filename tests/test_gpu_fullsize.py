@@ -115,23 +115,24 @@ def test_q100_pcg_first_iterations_match_oracle(ctx, q100):
     assert relerr(X.cpu().numpy(), ref["x"]) <= 1e-10
 
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "q1_100_oracle.json")
-GOLDEN_X = os.path.join(os.path.dirname(__file__), "golden", "q1_100_oracle_x.npz")
+def load_golden(E):
+    """FP64 oracle solves of the E^3 workload (written by
+    tests/golden/make_fullsize_golden.py, which calls only the oracle): x on
+    every 997th entry after every step k0 - 8 .. k0 + 8 around the oracle's
+    converged step count k0. A missing file fails the tests that need it."""
+    base = os.path.join(os.path.dirname(__file__), "golden", f"q1_{E}_oracle")
+    for f in (base + ".json", base + "_x.npz"):
+        assert os.path.exists(f), f"{f} is missing (tests/golden/make_fullsize_golden.py writes it)"
+    g = json.load(open(base + ".json"))
+    g["idx"] = np.asarray(g["sample_index"])
+    with np.load(base + "_x.npz") as z:
+        g["x"] = {k: z[k] for k in z.files}
+    return g
 
 
 @pytest.fixture(scope="module")
 def golden():
-    """FP64 oracle solves of this workload (written by
-    tests/golden/make_fullsize_golden.py, which calls only the oracle): x on
-    every 997th entry after every step k0 - 8 .. k0 + 8 around the oracle's
-    converged step count k0. A missing file fails the tests that need it."""
-    for f in (GOLDEN, GOLDEN_X):
-        assert os.path.exists(f), f"{f} is missing (tests/golden/make_fullsize_golden.py writes it)"
-    g = json.load(open(GOLDEN))
-    g["idx"] = np.asarray(g["sample_index"])
-    with np.load(GOLDEN_X) as z:
-        g["x"] = {k: z[k] for k in z.files}
-    return g
+    return load_golden(100)
 
 
 def sample_err(x, g, case, k=None):
@@ -315,3 +316,16 @@ def test_q150_multi_rhs_inference_scale(ctx):
     Xh = X.cpu().numpy()
     for c in (0, 15):
         assert true_relres(Ah, Xh[:, c], B[:, c]) <= 1e-8
+    # against the FP64 oracle's solves of load cases 0 and 1: the FP64 solve at
+    # its own step count (1e-10), the batch's FP32-factor columns against the
+    # oracle's converged solutions (1e-5)
+    g = load_golden(150)
+    assert g["alpha"] == finfo["alpha"] and g["n"] == prob.n
+    k = info0[0]["iters"]
+    e64 = sample_err(x0.cpu().numpy(), g, "traction0", k)
+    errs = [sample_err(Xh[:, c], g, f"traction{c}") for c in (0, 1)]
+    print(f"q150 against the oracle: FP64 load case 0 at step {k} (oracle {g['cases']['traction0']['iters']}): "
+          f"{e64:.2e}; batch columns 0, 1: {errs[0]:.2e}, {errs[1]:.2e}")
+    assert stop_agrees(k, g["cases"]["traction0"])
+    assert e64 <= FP64_EQUAL_K
+    assert max(errs) <= REDUCED_VS_FP64

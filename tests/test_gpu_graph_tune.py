@@ -98,3 +98,36 @@ def test_autotune_and_solve(ctx):
         assert infos[c]["status"] == 0 and abs(k - ref["iters"]) <= 1
         same_k = oracle.pcg(A_h, L, U, Bh[:, c], rtol=0.0, max_iter=k, max_replace=0)
         assert relerr(Xh[:, c], same_k["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_step_timing_phases(ctx, dt):
+    """Per-phase timing of eager steps: every phase of each recorded step is
+    measured (a positive mean), the record stops at 64 steps, timed steps give
+    the same result as untimed ones (the marks are events only), and
+    graph-replayed steps are not recorded."""
+    A_h = named_matrix("w:q1_40")
+    _, L, _, _ = oracle_factor("w:q1_40")
+    A = ctx.matrix(to_gpu(A_h))
+    P = ctx.prec(to_gpu(L), dt)
+    B = rhs(A.n, 16, 5)
+    ref = ctx.solve(A, P, B, rtol=0.0, max_iter=40, max_replace=0, block_width=16)
+    ctx.step_timing(True)
+    try:
+        got = ctx.solve(A, P, B, rtol=0.0, max_iter=40, max_replace=0, block_width=16)
+        t = ctx.step_timing_get()
+        print(dt, t)
+        same(got, ref)
+        assert t["steps"] == 40
+        for k in ctx.STEP_PHASES:
+            assert t[k] > 0.0, k
+        # a second, longer solve fills the record to its cap
+        ctx.step_timing(True)
+        ctx.solve(A, P, B, rtol=0.0, max_iter=100, max_replace=0, block_width=16)
+        assert ctx.step_timing_get()["steps"] == 64
+        # graph replay: nothing recorded
+        ctx.step_timing(True)
+        ctx.solve(A, P, B, rtol=0.0, max_iter=40, max_replace=0, block_width=16, use_graph=True)
+        assert ctx.step_timing_get()["steps"] == 0
+    finally:
+        ctx.step_timing(False)
