@@ -215,7 +215,13 @@ __global__ __launch_bounds__(kBlock, 3) void k_spmv_grp(const int32_t *__restric
         }
       }
     }
-    for (int64_t q = slot + QD * SLOTS; q < m; q += SLOTS) {  // rows longer than the window
+    // rows longer than the window (rare). The start is made opaque so that the
+    // compiler keeps its addresses in the loop: hoisted out of the group loop
+    // they outlive the registers and spill at every thread's start, which at
+    // one group pass per block writes more than the kernel's output.
+    int64_t qs = slot + QD * SLOTS;
+    asm volatile("" : "+v"(qs));
+    for (int64_t q = qs; q < m; q += SLOTS) {
       const int32_t j = ci[base + q];
       const double *xr = x + (int64_t)j * R + c0;
       double xv[CPL];
