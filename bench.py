@@ -96,6 +96,21 @@ def rz_extra_bytes(n, R):
     return 8 * n * R
 
 
+def xr_extra_bytes(n, R):
+    """What the forward solve of a PCG step moves beyond the solve itself when
+    it applies the previous step's update x += alpha p, r -= alpha w (FP32 /
+    BF16 factors on several columns): w, x and p read, r and x written (FP64;
+    r is the solve's right-hand side, already counted)."""
+    return 40 * n * R
+
+
+def step_fuses_xr(R):
+    """Whether the library's PCG step at this width applies the x, r update
+    in the forward solve (its default for FP32 / BF16 factors on 2-16
+    columns; ICPCG_FUSE_XR=0 turns it off)."""
+    return R > 1 and os.environ.get("ICPCG_FUSE_XR", "1") != "0"
+
+
 def recorded_traffic(kernel):
     """HBM bytes per launch from the committed counter summary, if the kernel
     source is unchanged since the counters were taken (else None)."""
@@ -419,6 +434,12 @@ def main():
     if args.kernels_only:
         R = args.nrhs if args.nrhs in (1, 2, 4, 8, 16) else 16
         kt = time_kernels(ctx, M, P32, R, args.kernel_reps, torch)
+        # eager steps of the headline solve, so that the step's own launches
+        # (the forward solve with the x, r update among them) are counted too:
+        # 7 iterations take 8 steps with the update in the forward solve (the
+        # first step's forward solve has no update to apply)
+        ctx.solve(M, P32, Bt, rtol=0.0, max_iter=7, max_replace=0, block_width=R)
+        torch.cuda.synchronize()
         # calibration for counter scaling: one plain device copy of 2^30 bytes each way
         src = torch.empty(2 ** 27, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -517,11 +538,18 @@ def main():
     spmv_b, trsvL_b = kernel_bytes(n, nnzA, nnzL, nsnL, R, 4, 8, 4, ngroups, gcols)
     _, trsvU_b = kernel_bytes(n, nnzA, nnzL, nsnU, R, 4, 4, 4, ngroups, gcols)
     trsvU_b += rz_extra_bytes(n, R)
+    # the step's forward solve also applies the previous step's x, r update
+    # where the library fuses it (the standalone launch is the plain solve)
+    fxr = step_fuses_xr(R)
     kernels = {
         "spmv": dict(s=kt["spmv"], bytes=spmv_b, gbs=spmv_b / kt["spmv"] / 1e9),
-        "trsv_L": dict(s=kt["trsv_L"], bytes=trsvL_b, gbs=trsvL_b / kt["trsv_L"] / 1e9),
+        "trsv_L": dict(s=kt["trsv_L"], bytes=trsvL_b, gbs=trsvL_b / kt["trsv_L"] / 1e9,
+                       bytes_in_step=trsvL_b + (xr_extra_bytes(n, R) if fxr else 0),
+                       counters="trsv_L_xr" if fxr else "trsv_L"),
         "trsv_U_rz": dict(s=kt["trsv_U_rz"], bytes=trsvU_b, gbs=trsvU_b / kt["trsv_U_rz"] / 1e9),
     }
+    for v in kernels.values():
+        v.setdefault("bytes_in_step", v["bytes"])
     for k_, v in kernels.items():
         log(f"kernel {k_}: {v['s'] * 1e3:.3f} ms, {v['gbs']:.0f} GB/s algorithmic")
     kernels_b = None
@@ -547,10 +575,12 @@ def main():
         kernels[k_]["in_step_s"] = in_step[k_]
     # the roofline's kernel: the largest of the three inside the step
     dom = max(kernels, key=lambda k_: kernels[k_]["in_step_s"])
-    gbs_in = kernels[dom]["bytes"] / kernels[dom]["in_step_s"] / 1e9
-    roof = dict(bound="hbm", kernel=dom, achieved=round(gbs_in, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=round(gbs_in / PEAK_HBM_GBS, 4), traffic=recorded_traffic(dom),
-                algorithmic_bytes_per_launch=kernels[dom]["bytes"], launch_ms=round(kernels[dom]["in_step_s"] * 1e3, 4),
+    gbs_in = kernels[dom]["bytes_in_step"] / kernels[dom]["in_step_s"] / 1e9
+    roof = dict(bound="hbm", kernel=dom + ("_xr" if dom == "trsv_L" and fxr else ""), achieved=round(gbs_in, 1),
+                peak=PEAK_HBM_GBS, unit="GB/s", frac=round(gbs_in / PEAK_HBM_GBS, 4),
+                traffic=recorded_traffic(kernels[dom].get("counters", dom)),
+                algorithmic_bytes_per_launch=kernels[dom]["bytes_in_step"],
+                launch_ms=round(kernels[dom]["in_step_s"] * 1e3, 4),
                 timing="mean of 64 in-step launches (events at the step's phase boundaries)")
 
     # the learned correction at this scale: one forward (inference) and one
@@ -635,11 +665,13 @@ def main():
         "variants": variants,
         "gnn_correction": gnn,
         "kernels": {k_: dict(ms_in_step=round(v["in_step_s"] * 1e3, 4),
-                             algorithmic_GBs_in_step=round(v["bytes"] / v["in_step_s"] / 1e9, 1),
-                             frac_hbm_peak_in_step=round(v["bytes"] / v["in_step_s"] / 1e9 / PEAK_HBM_GBS, 4),
+                             algorithmic_GBs_in_step=round(v["bytes_in_step"] / v["in_step_s"] / 1e9, 1),
+                             frac_hbm_peak_in_step=round(v["bytes_in_step"] / v["in_step_s"] / 1e9 / PEAK_HBM_GBS, 4),
+                             bytes_in_step=v["bytes_in_step"],
                              ms_standalone=round(v["s"] * 1e3, 4), algorithmic_GBs_standalone=round(v["gbs"], 1),
                              bytes=v["bytes"])
                     for k_, v in kernels.items()},
+        "step_fuses_xr": fxr,
         "step_phases_ms": {k_: round(v, 4) for k_, v in ph.items() if k_ != "steps"},
         "err_vs_oracle": err,
         "inference_150": inf150,

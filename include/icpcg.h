@@ -41,7 +41,7 @@
  *   ICPCG_SPMVG_SLOTS        entry slots per row group of the grouped SpMV
  *                            (16 or 32; default 32 below 8 columns, else 16)
  *   ICPCG_SPMVG_ITERS        row groups per lane group and block of the grouped
- *                            SpMV (default 1, 1, 2, 8, 16 at 1, 2, 4, 8, 16
+ *                            SpMV (default 1, 1, 2, 8, 1 at 1, 2, 4, 8, 16
  *                            columns)
  *   ICPCG_SPMV_SLOTS         entry slots per row of the plain SpMV (default 16)
  *   ICPCG_NO_ROW_GROUPS      when set, analysed matrices use the plain SpMV
@@ -53,6 +53,12 @@
  *                            r^T z itself (a separate pass does, as for FP64
  *                            factors and one column); default 1 (fused for
  *                            FP32 / BF16 factors on 2-16 columns)
+ *   ICPCG_FUSE_XR            0: a PCG step updates x and r (x += alpha p,
+ *                            r -= alpha w, ||r||^2) in a pass of its own;
+ *                            default 1: for FP32 / BF16 factors on 2-16
+ *                            columns the next step's forward solve applies the
+ *                            update ahead of its solve (same values; ||r||^2
+ *                            summed in another order)
  *   ICPCG_WAIT_LIMIT_US      time limit of one device-side dependency wait
  *                            (default 4 s); a wait that reaches it gives up,
  *                            the kernel finishes with a NaN in that place and
@@ -386,9 +392,12 @@ icpcg_status icpcg_solve_mat(icpcg_ctx *ctx, const icpcg_mat *M, const icpcg_pre
  * steps of each phase in ms: the forward solve; the backward solve (with r^T z
  * and beta where the solve forms them, else with their pass); the p update
  * (with the re-arming of y and z); w = A p; p^T w and alpha (empty where the
- * SpMV forms p^T w); the x and r update with ||r||. *steps (host) receives
- * the number of steps recorded (0: ms all 0). Errors: ICPCG_E_INVALID (null
- * arguments), ICPCG_E_DEVICE. */
+ * SpMV forms p^T w); the x and r update with ||r|| (empty where the next
+ * step's forward solve applies the update, see ICPCG_FUSE_XR; that solve's
+ * phase then includes it). *steps (host) receives the number of steps
+ * recorded (0: ms all 0): every eager step queued while recording, also those
+ * queued after the last column stopped, which return at once. Errors:
+ * ICPCG_E_INVALID (null arguments), ICPCG_E_DEVICE. */
 icpcg_status icpcg_step_timing(icpcg_ctx *ctx, int enable);
 icpcg_status icpcg_step_timing_get(icpcg_ctx *ctx, double *ms, int64_t *steps);
 

@@ -213,6 +213,7 @@ icpcg_status icpcg_create(icpcg_ctx **out, void *stream) {
   if (const char *e = std::getenv("ICPCG_TRSV_WAVES_PER_CU")) ctx->dev.trsv_waves_per_cu = std::atoi(e);
   if (const char *e = std::getenv("ICPCG_IC0_SYNC_FREE")) ctx->dev.ic0_sync_free = std::atoi(e) != 0;
   if (const char *e = std::getenv("ICPCG_FUSE_RZ")) ctx->dev.fuse_rz = std::atoi(e) != 0;
+  if (const char *e = std::getenv("ICPCG_FUSE_XR")) ctx->dev.fuse_xr = std::atoi(e) != 0;
   if (ensure_flags(ctx) != ICPCG_OK) {
     delete ctx;
     return ICPCG_E_NOMEM;
@@ -697,7 +698,8 @@ int spmv_pass(const icpcg_csr *A, const PassBuffers &b, const double *x, double 
 
 // `count` PCG steps of supplementary Algorithm 1 on stream s: z = L^-T L^-1 r,
 // r'z and beta (formed by the backward solve for FP32 / BF16 factors on several
-// columns), p = z + beta p, w = A p with p'w, then alpha, x, r and ||r||.
+// columns), p = z + beta p, w = A p with p'w, then alpha, x, r and ||r|| (for
+// those factors formed by the next step's forward solve, ahead of its solve).
 // Queued steps return at once when no column is active.
 int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const PassBuffers &b, int R,
                   int64_t max_iter, int count, hipStream_t s, bool timed = false) {
@@ -713,6 +715,22 @@ int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const
     ICPCG_HIP_TRY(hipEventRecord(ctx->tev[ctx->tsteps * icpcg_ctx::kPhaseMarks + m], s));
     return ICPCG_OK;
   };
+  // the x, r update of a step applied by the next step's forward solve, whose
+  // ||r||^2 then drives the stop tests (the updated x and r, and the tests,
+  // are those of the separate pass; the queued forward solve of a column that
+  // stops there goes unused)
+  const bool fxr = P->kind == ICPCG_PREC_FACTOR && trsv_fuses_xr(P, R, ctx->dev);
+  XrUpd xr{};
+  if (fxr) {
+    xr.X = b.X;
+    xr.r = b.r;
+    xr.p = b.p;
+    xr.w = b.w;
+    xr.cols = b.cols;
+    xr.partials = b.partials;
+    xr.max_iter = max_iter;
+    xr.flags = fl;
+  }
   for (int k = 0; k < count; ++k) {
     if ((st = mark(0))) return st;
     if (P->kind != ICPCG_PREC_FACTOR) {
@@ -720,7 +738,7 @@ int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const
                                static_cast<double *>(b.z), act, s)))
         return st;
     } else {
-      if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err, act))) return st;
+      if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err, act, RzDot{}, xr))) return st;
       if ((st = mark(1))) return st;
       // the backward solve also forms r^T z and beta where that pays
       const RzDot rz = trsv_fuses_rz(P, R, ctx->dev) ? RzDot{b.r, b.partials, b.cols, fl} : RzDot{};
@@ -747,7 +765,7 @@ int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const
       if ((st = mark(4))) return st;
     }
     if ((st = mark(5))) return st;
-    if ((st = pcg_update_xr(n, R, b.X, b.r, b.p, b.w, b.partials, b.cols, max_iter, fl, s))) return st;
+    if (!fxr && (st = pcg_update_xr(n, R, b.X, b.r, b.p, b.w, b.partials, b.cols, max_iter, fl, s))) return st;
     if ((st = mark(6))) return st;
     if (timed && ctx->tsteps < icpcg_ctx::kTimedSteps) ++ctx->tsteps;
   }

@@ -51,6 +51,7 @@ struct Device {
   int trsv_waves_per_cu = 0;  // 0: as many as fit
   bool ic0_sync_free = false;  // IC(0) in one sync-free launch instead of level launches
   bool fuse_rz = true;         // backward solves of a PCG step form r^T z where that pays
+  bool fuse_xr = true;         // forward solves of a PCG step apply the previous step's x, r update
   long long wall_hz = 100000000;  // wall_clock64 rate
   long long wait_ticks = 400000000;  // device-side wait limit (4 s)
 };
@@ -65,7 +66,7 @@ struct ColState {
   int repl;     // residual replacements
   int replace;  // replace r by the true residual on the next pass
   int zero_x;   // b = 0: x is set to 0
-  int pad;
+  int upd;      // alpha is set and x, r still await their update with it
 };
 
 struct SolveFlags {
@@ -281,11 +282,31 @@ struct RzDot {
   // a launch whose grid needs more is refused with ICPCG_E_INVALID
   int64_t partials_cap = -1;
 };
+// xr.X (nullable, forward solves of a PCG step): first the previous step's
+// update of every column c with cols[c].upd set, x += alpha p and r -= alpha w
+// (X, r, p, w: n x R, FP64; the solve's right-hand side is then the updated r,
+// read through `rhs`, which must be xr.r), with ||r||^2 of those columns into
+// block partials folded by k_rr_fin (iteration count and stop tests, as the
+// update_xr step does), which also clears upd.
+struct XrUpd {
+  double *X = nullptr;
+  double *r = nullptr;
+  const double *p = nullptr;
+  const double *w = nullptr;
+  ColState *cols = nullptr;
+  double *partials = nullptr;
+  int64_t partials_cap = -1;  // as in RzDot
+  int64_t max_iter = 0;
+  SolveFlags *flags = nullptr;
+};
 int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *out, int R,
          int64_t ld, hipStream_t s, const Device &dev, int *err, const int *active = nullptr,
-         const RzDot &rz = RzDot{});
+         const RzDot &rz = RzDot{}, const XrUpd &xr = XrUpd{});
 // whether the backward solve of a PCG step with this factor and width forms r^T z
 bool trsv_fuses_rz(const icpcg_prec *P, int R, const Device &dev);
+// whether the forward solve of a PCG step with this factor and width applies
+// the previous step's x, r update
+bool trsv_fuses_xr(const icpcg_prec *P, int R, const Device &dev);
 
 int prec_dL(const icpcg_prec *P, const void *Z, const void *Yb, const void *Rb, const void *Y,
             void *dL, int R, hipStream_t s);
@@ -314,6 +335,10 @@ int col_dot_out(int64_t n, int R, const double *r, const void *z, bool f32, doub
 int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const double *w,
                   double *partials, ColState *cols, int64_t max_iter, SolveFlags *flags,
                   hipStream_t s);
+// The stop tests of update_xr from ||r||^2 block partials formed elsewhere
+// (the forward solve that applies the update): columns with upd set only.
+int pcg_rr_finalize(int R, const double *partials, int nb, ColState *cols, int64_t max_iter, SolveFlags *flags,
+                    hipStream_t s);
 int pcg_true_residual(int64_t n, int R, const double *B, double *W, double *partials,
                       ColState *cols, int64_t max_iter, int max_replace, int final_pass,
                       SolveFlags *flags, hipStream_t s);

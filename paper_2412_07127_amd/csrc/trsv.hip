@@ -123,16 +123,34 @@ __device__ __forceinline__ void publish_elems(TA *p, const TA (&x)[CPL]) {
   }
 }
 
+// The previous PCG step's x and r update, for the forward solve that applies it.
+struct XrArgs {
+  double *X;
+  double *r;
+  const double *p;
+  const double *w;
+  const ColState *cols;
+};
+
 // RZ (backward solves inside the PCG loop): also r^T z of every column, from
 // the residual rows loaded with the right-hand side and each published row,
 // into block partials (a fixed per-lane order over the lane's items, then the
 // block tree).
-template <typename TV, typename TA, typename TR, int R, bool UPPER, int QD, int CPL, bool RZ>
+// XR (forward solves inside the PCG loop): the right-hand side is r after the
+// previous step's update r -= alpha w of the columns with upd set. The lanes
+// of slot 0 (which solve the diagonal block) form it from r and w loaded with
+// the right-hand side, store it with their published rows and sum it as
+// ||r||^2 into block partials like RZ; the lanes of slot 1 + u form
+// x += alpha p of row u. Each element of r is read once, by the lane that
+// then writes it, so reading it through the restrict-qualified rhs is sound.
+template <typename TV, typename TA, typename TR, int R, bool UPPER, int QD, int CPL, bool RZ, bool XR>
 __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci, const TV *__restrict__ val,
                                                  const SnItem *__restrict__ sched, int64_t nsn,
                                                  const TR *__restrict__ rhs, TA *out, int *err, long long limit,
                                                  const int *__restrict__ active, const double *__restrict__ rres,
-                                                 double *rz_partials) {
+                                                 double *rz_partials, XrArgs xr) {
+  static_assert(!(XR && (UPPER || RZ || R == 1 || CPL != 1 || 64 / R <= kSmax)),
+                "the x, r update goes with multi-column FP32 forward solves");
   if (active && *active == 0) return;  // every column of the solve has stopped
   using U = typename Flag<TA>::U;
   constexpr int LPR = R / CPL;                   // lanes per gathered row
@@ -158,6 +176,19 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
   double dot[CPL];
 #pragma unroll
   for (int cc = 0; cc < CPL; ++cc) dot[cc] = 0.0;
+  double alx[CPL];  // XR: alpha of the lane's columns, 0 where there is no update
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) alx[cc] = 0.0;
+  bool upx[CPL];
+#pragma unroll
+  for (int cc = 0; cc < CPL; ++cc) upx[cc] = false;
+  if constexpr (XR) {
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) {
+      upx[cc] = xr.cols[c0 + cc].upd != 0;
+      alx[cc] = xr.cols[c0 + cc].alpha;
+    }
+  }
   SnItem nxt;
   if (w0 < nsn) nxt = sched[w0];
   for (int64_t t = w0; t < nsn; t += nw) {
@@ -237,6 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
     TA dv[NDB];
     TA bv[kSmax][CPL];
     double rr[kSmax][CPL];  // residual rows (RZ)
+    double tx[kSmax];       // XR: w of the item's rows (slot 0); x and p of row slot - 1
     if constexpr (kRaw) {
 #pragma unroll
       for (int u = 0; u < kSmax; ++u) {
@@ -251,6 +283,13 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
         }
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) br[u][cc] = rhs[(int64_t)(a + uc) * R + c0 + cc];
+        if constexpr (XR) {
+          // one load per register in every lane, its address chosen by slot
+          const int ux = slot >= 1 && slot <= kSmax && slot - 1 < sz ? slot - 1 : 0;
+          const int64_t ex = (int64_t)(a + ux) * R + c0;
+          const double *src = slot == 0 ? xr.w + (int64_t)(a + uc) * R + c0 : u == 0 ? xr.X + ex : xr.p + ex;
+          tx[u] = *src;
+        }
         if constexpr (RZ) {
 #pragma unroll
           for (int cc = 0; cc < CPL; ++cc) rr[u][cc] = rres[(int64_t)(a + uc) * R + c0 + cc];
@@ -299,6 +338,20 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
         for (int cc = 0; cc < CPL; ++cc) xb[k][cc] = 0;
       }
     });
+    // XR: the update, formed here where its loads (issued before the gathers)
+    // have arrived by the time the first gather is waited for
+    // XR: the update, formed here, where its loads (issued before the gathers)
+    // have arrived by the time the first gather is waited for, and stored with
+    // the published rows (measured: 0.6% faster than storing it here)
+    double xn = 0.0;
+    if constexpr (XR) {
+#pragma unroll
+      for (int u = 0; u < kSmax; ++u) {
+        const double rn = fma(-alx[0], tx[u], br[u][0]);
+        br[u][0] = upx[0] ? rn : br[u][0];  // meaningful in slot 0
+      }
+      xn = fma(alx[0], tx[1], tx[0]);  // meaningful in slots 1 .. kSmax
+    }
     if constexpr (kBC) {
       // every pending entry is loaded again each round (one round trip per
       // round, no sleep): the first round that sees the last input ends the
@@ -475,9 +528,22 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
             for (int cc = 0; cc < CPL; ++cc) dot[cc] += rr[u][cc] * (double)xs[u][cc];
           }
       }
+      if constexpr (XR) {
+        if (upx[0]) {
+#pragma unroll
+          for (int u = 0; u < kSmax; ++u)
+            if (u < sz) {
+              xr.r[(int64_t)(a + u) * R + c0] = br[u][0];
+              dot[0] += br[u][0] * br[u][0];
+            }
+        }
+      }
+    }
+    if constexpr (XR) {
+      if (upx[0] && slot >= 1 && slot <= kSmax && slot - 1 < sz) xr.X[(int64_t)(a + slot - 1) * R + c0] = xn;
     }
   }
-  if constexpr (RZ) {
+  if constexpr (RZ || XR) {
     __shared__ double smem[CPL * kRedBlock];
     block_partials_cpl<R, CPL>(dot, rz_partials, smem);
   }
@@ -517,44 +583,49 @@ template <typename TA, int R> struct Depth {
   static constexpr int v = (40 + slots - 1) / slots;
 };
 
-template <typename TV, typename TA, typename TR, int R, bool UPPER, bool RZ>
+template <typename TV, typename TA, typename TR, int R, bool UPPER, bool RZ, bool XR>
 int launch(const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs, TA *out, hipStream_t s,
-           const Device &dev, int *err, const int *active, const RzDot &rz) {
-  if constexpr (RZ && R == 1) {  // not fused at one column (trsv_fuses_rz)
+           const Device &dev, int *err, const int *active, const RzDot &rz, const XrUpd &xr) {
+  if constexpr ((RZ || XR) && R == 1) {  // not fused at one column (trsv_fuses_rz, trsv_fuses_xr)
     return ICPCG_E_INVALID;
   } else {
   if (S.nsn == 0) return ICPCG_OK;
-  auto k = k_trsv<TV, TA, TR, R, UPPER, Depth<TA, R>::v, Cpl<TA, R>::v, RZ>;
+  auto k = k_trsv<TV, TA, TR, R, UPPER, Depth<TA, R>::v, Cpl<TA, R>::v, RZ, XR>;
   static int per_cu = 0;  // occupancy of this instantiation (same on every MI355X)
   int64_t grid = resident_blocks(k, dev, per_cu);
   const int64_t need = (S.nsn + 3) / 4;
   if (need < grid) grid = need;
   if (grid < 1) grid = 1;
-  if (RZ && rz.partials_cap >= 0 && grid * R > rz.partials_cap) {
-    set_error("trsv: the r^T z partials of " + std::to_string(grid) + " blocks x " + std::to_string(R) +
-              " columns exceed the " + std::to_string(rz.partials_cap) + " values of the given buffer");
+  const int64_t cap = RZ ? rz.partials_cap : xr.partials_cap;
+  if ((RZ || XR) && cap >= 0 && grid * R > cap) {
+    set_error(std::string("trsv: the ") + (RZ ? "r^T z" : "||r||^2") + " partials of " + std::to_string(grid) +
+              " blocks x " + std::to_string(R) + " columns exceed the " + std::to_string(cap) +
+              " values of the given buffer");
     return ICPCG_E_INVALID;
   }
+  const XrArgs xa{xr.X, xr.r, xr.p, xr.w, xr.cols};
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kBlock), 0, s, ci, val, S.items.as<SnItem>(), S.nsn, rhs, out,
-                     err, dev.wait_ticks, active, rz.r, rz.partials);
+                     err, dev.wait_ticks, active, rz.r, RZ ? rz.partials : xr.partials, xa);
   ICPCG_HIP_TRY(hipGetLastError());
   if constexpr (RZ) {
     if (rz.out) return dot_finalize_out(R, rz.partials, (int)grid, rz.out, s);
     return pcg_rz_finalize(R, rz.partials, (int)grid, rz.cols, rz.flags, s);
   }
+  if constexpr (XR) return pcg_rr_finalize(R, xr.partials, (int)grid, xr.cols, xr.max_iter, xr.flags, s);
   return ICPCG_OK;
   }
 }
 
-template <typename TV, typename TA, typename TR, bool UPPER, bool RZ = false>
+template <typename TV, typename TA, typename TR, bool UPPER, bool RZ = false, bool XR = false>
 int dispatch_r(int R, const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs, TA *out, hipStream_t s,
-               const Device &dev, int *err, const int *active, const RzDot &rz = RzDot{}) {
+               const Device &dev, int *err, const int *active, const RzDot &rz = RzDot{},
+               const XrUpd &xr = XrUpd{}) {
   switch (R) {
-    case 1: return launch<TV, TA, TR, 1, UPPER, RZ>(S, ci, val, rhs, out, s, dev, err, active, rz);
-    case 2: return launch<TV, TA, TR, 2, UPPER, RZ>(S, ci, val, rhs, out, s, dev, err, active, rz);
-    case 4: return launch<TV, TA, TR, 4, UPPER, RZ>(S, ci, val, rhs, out, s, dev, err, active, rz);
-    case 8: return launch<TV, TA, TR, 8, UPPER, RZ>(S, ci, val, rhs, out, s, dev, err, active, rz);
-    case 16: return launch<TV, TA, TR, 16, UPPER, RZ>(S, ci, val, rhs, out, s, dev, err, active, rz);
+    case 1: return launch<TV, TA, TR, 1, UPPER, RZ, XR>(S, ci, val, rhs, out, s, dev, err, active, rz, xr);
+    case 2: return launch<TV, TA, TR, 2, UPPER, RZ, XR>(S, ci, val, rhs, out, s, dev, err, active, rz, xr);
+    case 4: return launch<TV, TA, TR, 4, UPPER, RZ, XR>(S, ci, val, rhs, out, s, dev, err, active, rz, xr);
+    case 8: return launch<TV, TA, TR, 8, UPPER, RZ, XR>(S, ci, val, rhs, out, s, dev, err, active, rz, xr);
+    case 16: return launch<TV, TA, TR, 16, UPPER, RZ, XR>(S, ci, val, rhs, out, s, dev, err, active, rz, xr);
     default:
       set_error("trsv: unsupported block width " + std::to_string(R));
       return ICPCG_E_INVALID;
@@ -572,11 +643,35 @@ bool trsv_fuses_rz(const icpcg_prec *P, int R, const Device &dev) {
   return dev.fuse_rz && P->dtype != ICPCG_F64 && R > 1;
 }
 
+// The x, r update rides on the forward solve where the solve has registers to
+// spare for its operands and is bound by its dependency chain, not by memory:
+// FP32 arithmetic on 2-16 columns. Its separate pass streams x, r, p and w
+// (48 bytes per entry, about 0.43 ms per step at 16 columns of 3.06M rows).
+bool trsv_fuses_xr(const icpcg_prec *P, int R, const Device &dev) {
+  return dev.fuse_xr && P->dtype != ICPCG_F64 && R > 1;
+}
+
 // `out` must hold the pending pattern in every entry on entry.
 int trsv(const icpcg_prec *P, bool upper, const void *rhs, bool rhs_f64, void *out, int R, int64_t, hipStream_t s,
-         const Device &dev, int *err, const int *active, const RzDot &rz) {
+         const Device &dev, int *err, const int *active, const RzDot &rz, const XrUpd &xr) {
   const int32_t *ci = upper ? P->uci.as<int32_t>() : P->lci.as<int32_t>();
   const TriSchedule &S = upper ? P->su : P->sl;
+  if (xr.X) {
+    // the forward solve of a PCG step with the previous step's x, r update
+    if (upper || !rhs_f64 || rz.partials || rhs != xr.r || !xr.r || !xr.p || !xr.w || !xr.cols || !xr.partials ||
+        !xr.flags || !trsv_fuses_xr(P, R, dev)) {
+      set_error("trsv: the x, r update only with the forward solve of a PCG step (FP32 or BF16 factor, 2-16 "
+                "columns, right-hand side r)");
+      return ICPCG_E_INVALID;
+    }
+    if (P->dtype == ICPCG_F32)
+      return dispatch_r<float, float, double, false, false, true>(R, S, ci, P->lval_lo.as<float>(),
+                                                                  (const double *)rhs, (float *)out, s, dev, err,
+                                                                  active, RzDot{}, xr);
+    return dispatch_r<unsigned short, float, double, false, false, true>(
+        R, S, ci, P->lval_lo.as<unsigned short>(), (const double *)rhs, (float *)out, s, dev, err, active, RzDot{},
+        xr);
+  }
   if (rz.partials) {
     // the backward solve of a PCG step (right-hand side in the factor's precision)
     if (!upper || rhs_f64 || !trsv_fuses_rz(P, R, dev)) {

@@ -10,6 +10,8 @@
 //   dot_pw        p^T w, after the SpMV (fused in the plain
 //                 row kernel)                               -> alpha = r^T z / p^T w
 //   update_xr     x += alpha p, r -= alpha w, ||r||^2        -> iteration count, stop test
+//                 (for FP32 / BF16 factors on several columns applied by the
+//                 next step's forward solve, k_rr_fin alone then)
 //   true_residual b - A x, ||b - A x||^2                     -> accept / replace / give up
 // Converged or failed columns are frozen (their x, r, p are no longer touched).
 // Steps queued after every column stopped return at once (n_active == 0).
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_init_fin(const double *partials, int
     cs.status = ICPCG_OK;
     cs.conv = 0;
     cs.active = 0;
-    cs.pad = 0;
+    cs.upd = 0;
     if (cs.bb == 0.0) {
       cs.zero_x = 1;  // b = 0: x = 0 after 0 iterations
       cs.rr = cs.trr = 0.0;
@@ -192,7 +194,10 @@ __global__ __launch_bounds__(kBlock) void k_pw_fin(const double *partials, int n
       cs.pw = pw;
       if (!isfinite(pw)) { cs.status = ICPCG_E_NONFINITE; cs.active = 0; }
       else if (!(pw > 0.0)) { cs.status = ICPCG_E_BREAKDOWN; cs.active = 0; }
-      else cs.alpha = cs.rz / pw;
+      else {
+        cs.alpha = cs.rz / pw;
+        cs.upd = 1;
+      }
     }
   }
 }
@@ -217,8 +222,8 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int64_t n, double *__restr
   ICPCG_GRID_LOOP(e, n * R) {
     const int c = (int)(e % R);
     if (act[c]) {
-      X[e] = X[e] + alpha[c] * p[e];
-      const double ri = r[e] - alpha[c] * w[e];
+      X[e] = fma(alpha[c], p[e], X[e]);
+      const double ri = fma(-alpha[c], w[e], r[e]);
       r[e] = ri;
       acc += ri * ri;
     }
@@ -227,7 +232,9 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int64_t n, double *__restr
   block_partials<R, 1>(v, partials, smem);
 }
 
-template <int R>
+// FUSED: the partials come from the forward solve that applied the update,
+// which covers the columns with upd set (the others kept their x and r).
+template <int R, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_rr_fin(const double *partials, int nb, ColState *cols, int64_t max_iter,
                                                    SolveFlags *flags) {
   if (flags->n_active == 0) return;
@@ -237,7 +244,9 @@ __global__ __launch_bounds__(kBlock) void k_rr_fin(const double *partials, int n
   const int t = threadIdx.x;
   if (t < R) {
     ColState &cs = cols[t];
-    if (cs.active) {
+    const bool updated = FUSED ? cs.upd != 0 : cs.active != 0;
+    cs.upd = 0;
+    if (cs.active && updated) {
       cs.iters += 1;
       cs.rr = out[t];
       if (!isfinite(cs.rr)) { cs.status = ICPCG_E_NONFINITE; cs.active = 0; }
@@ -448,8 +457,16 @@ int pcg_update_xr(int64_t n, int R, double *X, double *r, const double *p, const
   const unsigned g = vec_grid(n, R);
   ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_update_xr<RR>, dim3(g), dim3(kBlock), 0, s, n, X, r, p, w, cols, partials,
                                        flags));
-  ICPCG_R_SWITCH(R, hipLaunchKernelGGL(k_rr_fin<RR>, dim3(1), dim3(kBlock), 0, s, partials, (int)g, cols, max_iter,
-                                       flags));
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_rr_fin<RR, false>), dim3(1), dim3(kBlock), 0, s, partials, (int)g, cols,
+                                       max_iter, flags));
+  ICPCG_HIP_TRY(hipGetLastError());
+  return ICPCG_OK;
+}
+
+int pcg_rr_finalize(int R, const double *partials, int nb, ColState *cols, int64_t max_iter, SolveFlags *flags,
+                    hipStream_t s) {
+  ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_rr_fin<RR, true>), dim3(1), dim3(kBlock), 0, s, partials, nb, cols,
+                                       max_iter, flags));
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
 }

@@ -103,9 +103,13 @@ def test_autotune_and_solve(ctx):
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_step_timing_phases(ctx, dt):
     """Per-phase timing of eager steps: every phase of each recorded step is
-    measured (a positive mean), the record stops at 64 steps, timed steps give
+    measured (a positive mean; the x, r update phase is empty where the forward
+    solve applies the update), the record stops at 64 steps, timed steps give
     the same result as untimed ones (the marks are events only), and
-    graph-replayed steps are not recorded."""
+    graph-replayed steps are not recorded. With the update in the forward
+    solve, the last iteration's stop test runs in the step after it: 41 steps
+    for 40 iterations, queued in batches of 8 (the queued steps after the stop
+    return at once and are recorded too)."""
     A_h = named_matrix("w:q1_40")
     _, L, _, _ = oracle_factor("w:q1_40")
     A = ctx.matrix(to_gpu(A_h))
@@ -118,9 +122,13 @@ def test_step_timing_phases(ctx, dt):
         t = ctx.step_timing_get()
         print(dt, t)
         same(got, ref)
-        assert t["steps"] == 40
+        fused_xr = dt != "f64"
+        assert t["steps"] == (48 if fused_xr else 40)
         for k in ctx.STEP_PHASES:
-            assert t[k] > 0.0, k
+            if fused_xr and k == "update_xr":
+                assert t[k] >= 0.0
+            else:
+                assert t[k] > 0.0, k
         # a second, longer solve fills the record to its cap
         ctx.step_timing(True)
         ctx.solve(A, P, B, rtol=0.0, max_iter=100, max_replace=0, block_width=16)

@@ -52,6 +52,23 @@ def ctx_unfused():
     return c
 
 
+@pytest.fixture(scope="module")
+def ctx_sep_xr():
+    """A context whose PCG steps update x and r in their own pass (the forward
+    solve does not apply them)."""
+    torch.cuda.set_device(0)
+    old = os.environ.get("ICPCG_FUSE_XR")
+    os.environ["ICPCG_FUSE_XR"] = "0"
+    try:
+        c = pkg.Context()
+    finally:
+        if old is None:
+            del os.environ["ICPCG_FUSE_XR"]
+        else:
+            os.environ["ICPCG_FUSE_XR"] = old
+    return c
+
+
 def to_gpu(A):
     return pkg.CSR.from_numpy(*A, device="cuda")
 
@@ -197,6 +214,41 @@ def test_multi_rhs_reduced_precision_pcg(ctx, ctx_unfused, key, E, dt, fused):
           f"converged vs FP64 oracle {worst['e64']:.2e}")
     assert worst["e3"] <= 10 * APPLY_TOL[dt]
     assert worst["e64"] <= 1e-5
+
+
+@pytest.mark.parametrize("key,E,R", [("q1_8", 8, 2), ("q1_8", 8, 16), ("q1_40", 40, 16)])
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_pcg_xr_in_forward_solve_equals_separate_pass(ctx, ctx_sep_xr, key, E, R, dt):
+    """The forward solve that applies the previous step's x, r update forms the
+    same values as the separate pass (the same fused multiply-adds), so the
+    iterates are bit-identical at equal step counts; only ||r||^2 is summed in
+    another order, which can move a converged stop by one step at most."""
+    prob, _ = workload_problem(key)
+    Ah = (prob.row_ptr, prob.col, prob.val)
+    _, L, U, _ = oracle_factor(f"w:{key}")
+    B = torch.from_numpy(np.ascontiguousarray(traction_loads(E, 16, 2000 + E)[:, :R])).cuda()
+    for k in (1, 2, 7):
+        outs = []
+        for c in (ctx, ctx_sep_xr):
+            P = c.prec(to_gpu(L), dt)
+            outs.append(c.solve(to_gpu(Ah), P, B, rtol=0.0, max_iter=k, max_replace=0, block_width=R))
+        (Xa, ia), (Xb, ib) = outs
+        assert [i["iters"] for i in ia] == [i["iters"] for i in ib] == [k] * R
+        assert [i["status"] for i in ia] == [i["status"] for i in ib] == [pkg._lib.E_MAXITER] * R
+        assert torch.equal(Xa, Xb), k
+    outs = []
+    for c in (ctx, ctx_sep_xr):
+        P = c.prec(to_gpu(L), dt)
+        outs.append(c.solve(to_gpu(Ah), P, B, rtol=1e-8, block_width=R))
+    (Xa, ia), (Xb, ib) = outs
+    same = 0
+    for c in range(R):
+        assert ia[c]["status"] == ib[c]["status"] == 0
+        assert abs(ia[c]["iters"] - ib[c]["iters"]) <= 1
+        if ia[c]["iters"] == ib[c]["iters"]:
+            same += 1
+            assert torch.equal(Xa[:, c], Xb[:, c]), c
+    print(f"{key} R={R} {dt}: {same} of {R} columns stop at the same step (bit-identical x there)")
 
 
 # ------------------------------------------------------------ autograd
