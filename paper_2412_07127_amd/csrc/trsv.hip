@@ -338,8 +338,6 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
         for (int cc = 0; cc < CPL; ++cc) xb[k][cc] = 0;
       }
     });
-    // XR: the update, formed here where its loads (issued before the gathers)
-    // have arrived by the time the first gather is waited for
     // XR: the update, formed here, where its loads (issued before the gathers)
     // have arrived by the time the first gather is waited for, and stored with
     // the published rows (measured: 0.6% faster than storing it here)
