@@ -36,6 +36,10 @@
 //    Partial sums meet in a fixed butterfly (deterministic).
 //  * Factor values may be FP64, FP32 or bfloat16 (widened to FP32); FP32 and
 //    bfloat16 factors run FP32 arithmetic.
+//  * Inside a PCG step with an FP32 or bfloat16 factor on several columns the
+//    solves carry the step's streaming work: the forward solve first applies
+//    the previous step's x, r update to its rows (XR) and the backward solve
+//    forms r^T z (RZ), each summed into block partials in a fixed order.
 #include <utility>
 
 #include "reduce.hpp"
