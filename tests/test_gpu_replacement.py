@@ -13,6 +13,8 @@ Three cases force the replacement branch deterministically:
     its own one-column iteration.
 """
 
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -30,6 +32,22 @@ pytestmark = pytest.mark.gpu
 def ctx():
     torch.cuda.set_device(0)
     return pkg.Context()
+
+
+@pytest.fixture(scope="module")
+def ctx_sep_xr():
+    """A context whose PCG steps update x and r in their own pass."""
+    torch.cuda.set_device(0)
+    old = os.environ.get("ICPCG_FUSE_XR")
+    os.environ["ICPCG_FUSE_XR"] = "0"
+    try:
+        c = pkg.Context()
+    finally:
+        if old is None:
+            del os.environ["ICPCG_FUSE_XR"]
+        else:
+            os.environ["ICPCG_FUSE_XR"] = old
+    return c
 
 
 def _csr_np(M):
@@ -107,7 +125,7 @@ def _breakdown_block(L8, A8, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
-def test_replacement_after_last_column_breaks_down(ctx, q8, dtype):
+def test_replacement_after_last_column_breaks_down(ctx, ctx_sep_xr, q8, dtype):
     Ah8, L8, _, b8 = q8
     A, L, n1 = _breakdown_block(L8, Ah8, dtype)
     U = oracle.transpose(*L)
@@ -137,3 +155,16 @@ def test_replacement_after_last_column_breaks_down(ctx, q8, dtype):
     # tolerance is crossed by up to two
     assert abs(info[0]["iters"] - refs[0]["iters"]) <= (1 if dtype == "f64" else 2)
     assert e <= 1e-10
+    if dtype != "f64":
+        # the same block with the x, r update in its own pass instead of the
+        # forward solve: same statuses and counts; where both stop at the same
+        # step the iterates are the same bits (||r||^2 alone is summed in
+        # another order, which may move a 1e-14 stop by one step)
+        X2, info2 = ctx_sep_xr.solve(pkg.CSR.from_numpy(*A), ctx_sep_xr.prec(pkg.CSR.from_numpy(*L), dtype),
+                                     torch.from_numpy(B).cuda(), rtol=1e-14, max_replace=1, max_iter=2000,
+                                     block_width=2)
+        for c in range(2):
+            assert info2[c]["status"] == info[c]["status"] and info2[c]["replacements"] == info[c]["replacements"]
+            assert abs(info2[c]["iters"] - info[c]["iters"]) <= 1
+            if info2[c]["iters"] == info[c]["iters"]:
+                assert torch.equal(X2[:, c], X[:, c]), c
