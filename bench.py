@@ -104,6 +104,20 @@ def xr_extra_bytes(n, R):
     return 40 * n * R
 
 
+def rearm_extra_bytes(n, R):
+    """What the backward solve of a PCG step writes beyond the solve itself
+    where it forms r^T z (FP32 / BF16 factors on 2-16 columns): y re-armed as
+    pending once read (FP32)."""
+    return 4 * n * R
+
+
+def step_fuses_rz(R):
+    """Whether the library's PCG step at this width forms r^T z in the
+    backward solve, which then also re-arms y (its default for FP32 / BF16
+    factors on 2-16 columns; ICPCG_FUSE_RZ=0 turns it off)."""
+    return R > 1 and os.environ.get("ICPCG_FUSE_RZ", "1") != "0"
+
+
 def step_fuses_xr(R):
     """Whether the library's PCG step at this width applies the x, r update
     in the forward solve (its default for FP32 / BF16 factors on 2-16
@@ -546,7 +560,9 @@ def main():
         "trsv_L": dict(s=kt["trsv_L"], bytes=trsvL_b, gbs=trsvL_b / kt["trsv_L"] / 1e9,
                        bytes_in_step=trsvL_b + (xr_extra_bytes(n, R) if fxr else 0),
                        counters="trsv_L_xr" if fxr else "trsv_L"),
-        "trsv_U_rz": dict(s=kt["trsv_U_rz"], bytes=trsvU_b, gbs=trsvU_b / kt["trsv_U_rz"] / 1e9),
+        "trsv_U_rz": dict(s=kt["trsv_U_rz"], bytes=trsvU_b, gbs=trsvU_b / kt["trsv_U_rz"] / 1e9,
+                          bytes_in_step=trsvU_b + (rearm_extra_bytes(n, R) if step_fuses_rz(R) else 0),
+                          counters="trsv_U_rz_step" if step_fuses_rz(R) else "trsv_U_rz"),
     }
     for v in kernels.values():
         v.setdefault("bytes_in_step", v["bytes"])

@@ -740,8 +740,16 @@ int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const
     } else {
       if ((st = trsv(P, false, b.r, true, b.y, R, R, s, ctx->dev, err, act, RzDot{}, xr))) return st;
       if ((st = mark(1))) return st;
-      // the backward solve also forms r^T z and beta where that pays
-      const RzDot rz = trsv_fuses_rz(P, R, ctx->dev) ? RzDot{b.r, b.partials, b.cols, fl} : RzDot{};
+      // the backward solve also forms r^T z and beta where that pays, and then
+      // re-arms y (its right-hand side) for the next step's forward solve
+      RzDot rz{};
+      if (trsv_fuses_rz(P, R, ctx->dev)) {
+        rz.r = b.r;
+        rz.partials = b.partials;
+        rz.cols = b.cols;
+        rz.flags = fl;
+        rz.rearm_rhs = true;
+      }
       if ((st = trsv(P, true, b.y, !lo, b.z, R, R, s, ctx->dev, err, act, rz))) return st;
     }
     if (P->kind != ICPCG_PREC_FACTOR && (st = mark(1))) return st;
@@ -749,7 +757,8 @@ int enqueue_steps(icpcg_ctx *ctx, const icpcg_csr *A, const icpcg_prec *P, const
         (st = pcg_dot_rz(n, R, b.r, b.z, lo, b.partials, b.cols, fl, s)))
       return st;
     if ((st = mark(2))) return st;
-    if ((st = pcg_update_p(n, R, b.z, lo, b.p, b.y, b.cols, fl, s))) return st;
+    const bool y_rearmed = P->kind == ICPCG_PREC_FACTOR && trsv_fuses_rz(P, R, ctx->dev);
+    if ((st = pcg_update_p(n, R, b.z, lo, b.p, y_rearmed ? nullptr : b.y, b.cols, fl, s))) return st;
     if ((st = mark(3))) return st;
     if (b.grec) {
       // w = A p, then p^T w and alpha in their own pass (what the grouped

@@ -281,6 +281,9 @@ struct RzDot {
   // doubles available at `partials` (< 0: sized by the caller for any grid);
   // a launch whose grid needs more is refused with ICPCG_E_INVALID
   int64_t partials_cap = -1;
+  // the solve also re-arms its right-hand side as pending once read (the
+  // next step's forward solve writes it), in place of the p update
+  bool rearm_rhs = false;
 };
 // xr.X (nullable, forward solves of a PCG step): first the previous step's
 // update of every column c with cols[c].upd set, x += alpha p and r -= alpha w
@@ -319,7 +322,8 @@ int pcg_init(int64_t n, int R, const double *B, const double *W, double *r, doub
 int pcg_zero_x(int64_t n, int R, double *X, const ColState *cols, hipStream_t s);
 int pcg_dot_rz(int64_t n, int R, const double *r, const void *z, bool f32, double *partials,
                ColState *cols, SolveFlags *flags, hipStream_t s);
-// p = z + beta p; then y and z (read in place) are re-armed as pending
+// p = z + beta p; then z (read in place) and y are re-armed as pending (y
+// null: y was re-armed by the backward solve)
 int pcg_update_p(int64_t n, int R, void *z, bool f32, double *p, void *y, const ColState *cols,
                  const SolveFlags *flags, hipStream_t s);
 int pcg_pw_finalize(int R, const double *partials, int nb, ColState *cols, const SolveFlags *flags,

@@ -152,7 +152,8 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
                                                  const SnItem *__restrict__ sched, int64_t nsn,
                                                  const TR *__restrict__ rhs, TA *out, int *err, long long limit,
                                                  const int *__restrict__ active, const double *__restrict__ rres,
-                                                 double *rz_partials, XrArgs xr) {
+                                                 double *rz_partials, XrArgs xr,
+                                                 typename Flag<TR>::U *rhs_rearm) {
   static_assert(!(XR && (UPPER || RZ || R == 1 || CPL != 1 || 64 / R <= kSmax)),
                 "the x, r update goes with multi-column FP32 forward solves");
   if (active && *active == 0) return;  // every column of the solve has stopped
@@ -529,6 +530,16 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
 #pragma unroll
             for (int cc = 0; cc < CPL; ++cc) dot[cc] += rr[u][cc] * (double)xs[u][cc];
           }
+        // the right-hand side rows were read once, by this item: re-armed as
+        // pending for the next step's forward solve, which writes them
+        if (rhs_rearm) {
+#pragma unroll
+          for (int u = 0; u < kSmax; ++u)
+            if (u < sz) {
+#pragma unroll
+              for (int cc = 0; cc < CPL; ++cc) rhs_rearm[(int64_t)(a + u) * R + c0 + cc] = Flag<TR>::kPending;
+            }
+        }
       }
       if constexpr (XR) {
         if (upx[0]) {
@@ -607,7 +618,8 @@ int launch(const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs
   }
   const XrArgs xa{xr.X, xr.r, xr.p, xr.w, xr.cols};
   hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kBlock), 0, s, ci, val, S.items.as<SnItem>(), S.nsn, rhs, out,
-                     err, dev.wait_ticks, active, rz.r, RZ ? rz.partials : xr.partials, xa);
+                     err, dev.wait_ticks, active, rz.r, RZ ? rz.partials : xr.partials, xa,
+                     RZ && rz.rearm_rhs ? reinterpret_cast<typename Flag<TR>::U *>(const_cast<TR *>(rhs)) : nullptr);
   ICPCG_HIP_TRY(hipGetLastError());
   if constexpr (RZ) {
     if (rz.out) return dot_finalize_out(R, rz.partials, (int)grid, rz.out, s);

@@ -6,7 +6,8 @@
 //   dot_rz        r^T z (formed by the backward triangular
 //                 solve for FP32 / BF16 factors on several
 //                 columns, k_rz_fin alone then)             -> beta = r_k^T z_k / r_{k-1}^T z_{k-1}
-//   update_p      p = z + beta p (also re-arms y, z as pending for the next solves)
+//   update_p      p = z + beta p (also re-arms z, and y where the backward solve
+//                 did not, as pending for the next solves)
 //   dot_pw        p^T w, after the SpMV (fused in the plain
 //                 row kernel)                               -> alpha = r^T z / p^T w
 //   update_xr     x += alpha p, r -= alpha w, ||r||^2        -> iteration count, stop test
@@ -157,8 +158,9 @@ __global__ __launch_bounds__(kBlock) void k_dot_out(const double *partials, int 
 // ------------------------------------------------------------- update p
 
 // z is read and then re-armed as pending in place (one pointer, so the
-// compiler keeps each read before the store to the same element).
-template <int R, typename TZ>
+// compiler keeps each read before the store to the same element). Y: y is
+// re-armed here too (else the backward solve did it).
+template <int R, typename TZ, bool Y>
 __global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, TZ *z, double *__restrict__ p, TZ *__restrict__ y,
                                                      const ColState *__restrict__ cols, const SolveFlags *flags) {
   if (flags->n_active == 0) return;
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, TZ *z, double *_
   ICPCG_GRID_LOOP(e, n * R) {
     const int c = (int)(e % R);
     if (act[c]) p[e] = (double)z[e] + beta[c] * p[e];
-    y[e] = Pending<TZ>::get();
+    if (Y) y[e] = Pending<TZ>::get();
     z[e] = Pending<TZ>::get();
   }
 }
@@ -427,12 +429,18 @@ int col_dot_out(int64_t n, int R, const double *r, const void *z, bool f32, doub
 int pcg_update_p(int64_t n, int R, void *z, bool f32, double *p, void *y, const ColState *cols,
                  const SolveFlags *flags, hipStream_t s) {
   const unsigned g = vec_grid(n, R);
-  if (f32) {
-    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, float>), dim3(g), dim3(kBlock), 0, s, n, (float *)z, p,
-                                         (float *)y, cols, flags));
+  if (f32 && y) {
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, float, true>), dim3(g), dim3(kBlock), 0, s, n, (float *)z,
+                                         p, (float *)y, cols, flags));
+  } else if (f32) {
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, float, false>), dim3(g), dim3(kBlock), 0, s, n, (float *)z,
+                                         p, (float *)y, cols, flags));
+  } else if (y) {
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, double, true>), dim3(g), dim3(kBlock), 0, s, n,
+                                         (double *)z, p, (double *)y, cols, flags));
   } else {
-    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, double>), dim3(g), dim3(kBlock), 0, s, n, (double *)z, p,
-                                         (double *)y, cols, flags));
+    ICPCG_R_SWITCH(R, hipLaunchKernelGGL((k_update_p<RR, double, false>), dim3(g), dim3(kBlock), 0, s, n,
+                                         (double *)z, p, (double *)y, cols, flags));
   }
   ICPCG_HIP_TRY(hipGetLastError());
   return ICPCG_OK;
