@@ -37,7 +37,11 @@
  * Tuning knobs (environment, read when a context is created or a kernel is
  * first chosen; the defaults are the measured best on MI355X):
  *   ICPCG_TRSV_WAVES_PER_CU  cap on the resident waves per CU of the
- *                            triangular solves (default: all that fit)
+ *                            triangular solves (default: all that fit; for
+ *                            16 columns with an FP32 / BF16 factor at most
+ *                            about 2.8 supernode levels' worth, e.g. 16 at
+ *                            100^3; a value above what fits means all that
+ *                            fit)
  *   ICPCG_SPMVG_SLOTS        entry slots per row group of the grouped SpMV
  *                            (16 or 32; default 32 below 8 columns, else 16)
  *   ICPCG_SPMVG_ITERS        row groups per lane group and block of the grouped

@@ -40,6 +40,8 @@
 //    solves carry the step's streaming work: the forward solve first applies
 //    the previous step's x, r update to its rows (XR) and the backward solve
 //    forms r^T z (RZ), each summed into block partials in a fixed order.
+#include <algorithm>
+#include <cmath>
 #include <utility>
 
 #include "reduce.hpp"
@@ -562,10 +564,11 @@ __global__ __launch_bounds__(kBlock) void k_trsv(const int32_t *__restrict__ ci,
   }
 }
 
-// Waves the solve keeps resident: all that fit (the static round-robin needs
-// the whole grid resident), or fewer when ICPCG_TRSV_WAVES_PER_CU asks.
+// Waves the solve keeps resident (the static round-robin needs the whole grid
+// resident): all that fit, at most `cap` per CU where the kernel has a
+// measured best (cap > 0), or the number ICPCG_TRSV_WAVES_PER_CU asks.
 template <typename K>
-int64_t resident_blocks(K kernel, const Device &dev, int &cached) {
+int64_t resident_blocks(K kernel, const Device &dev, int &cached, int cap = 0) {
   if (cached <= 0) {
     int q = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, kernel, kBlock, 0) != hipSuccess || q < 1) {
@@ -575,8 +578,9 @@ int64_t resident_blocks(K kernel, const Device &dev, int &cached) {
     cached = q;
   }
   int per_cu = cached;
-  if (dev.trsv_waves_per_cu > 0) {
-    const int want = (dev.trsv_waves_per_cu + 3) / 4;
+  if (dev.trsv_waves_per_cu > 0) cap = dev.trsv_waves_per_cu;
+  if (cap > 0) {
+    const int want = (cap + 3) / 4;
     if (want < per_cu) per_cu = want;
   }
   return (int64_t)per_cu * dev.num_cu;
@@ -605,7 +609,21 @@ int launch(const TriSchedule &S, const int32_t *ci, const TV *val, const TR *rhs
   if (S.nsn == 0) return ICPCG_OK;
   auto k = k_trsv<TV, TA, TR, R, UPPER, Depth<TA, R>::v, Cpl<TA, R>::v, RZ, XR>;
   static int per_cu = 0;  // occupancy of this instantiation (same on every MI355X)
-  int64_t grid = resident_blocks(k, dev, per_cu);
+  // 16 columns in FP32 arithmetic: as many resident waves as about 2.8 levels
+  // of supernodes, where that is fewer than fit (measured in the PCG step at
+  // 100^3, 1464 supernodes per level: 16 waves per CU beat 8, 12 and all that
+  // fit, 20 (forward solve with the x, r update 1.68 -> 1.63 ms, backward with
+  // r^T z 1.49 -> 1.46 ms); at 150^3 and in the multicolour orders, with more
+  // supernodes per level, fewer waves than fit were slower)
+  int wave_cap = 0;
+  if constexpr (R == 16 && sizeof(TA) == 4) {
+    if (S.nlev > 0) {
+      const double waves = 2.8 * (double)S.nsn / (double)S.nlev;
+      const long blocks = std::lround(waves / (4.0 * dev.num_cu));
+      wave_cap = 4 * (int)std::max(1L, std::min(blocks, 64L));
+    }
+  }
+  int64_t grid = resident_blocks(k, dev, per_cu, wave_cap);
   const int64_t need = (S.nsn + 3) / 4;
   if (need < grid) grid = need;
   if (grid < 1) grid = 1;
